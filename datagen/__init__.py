@@ -1,0 +1,301 @@
+"""Seeded synthetic inputs for BinSketch: sparse binary corpora in CSR form and
+random maps pi:[d] -> [N].
+
+This module holds none of the sketching or estimation arithmetic. It only draws
+inputs, and it is the one module that both the CPU oracle's tests and the GPU
+path's tests and benchmark use. The random map of the BinSketch definition
+(Section 3, Definition "BinSketch": pi is one of the N^d functions from
+{1..d} to {1..N}, so every coordinate is mapped independently and uniformly)
+is drawn here and handed to both sides as an input table.
+
+Conventions (0-based, where the paper counts from 1):
+  * a binary vector a in {0,1}^d is a sorted list of its set indices (the
+    sparse representation of Section 1.1), stored row after row in CSR form:
+    ``indptr`` int32[n+1], ``indices`` int32[nnz];
+  * ``pi`` is int32[d] with values in [0, N).
+
+Generators:
+  * ``splitmix64``: Steele, Lea and Flood, "Fast splittable pseudorandom number
+    generators" (OOPSLA 2014); the table entry for coordinate i is the i-th
+    output of the stream started at ``seed``, reduced to [0, N) by the
+    multiply-high map (x >> 32) * N >> 32, which is exactly uniform when N is a
+    power of two.
+  * row lengths: Zipf(s) truncated to [lo, hi], or a rounded log-normal;
+  * feature ids: popularity proportional to rank^-s (Zipf), drawn without
+    replacement within a row by successive sampling (draw with replacement,
+    keep first occurrences), ranks mapped to ids through a seeded permutation.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
+    """Outputs start .. start+count-1 of the SplitMix64 stream for ``seed``."""
+    i = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + i * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def random_map(d: int, N: int, seed: int) -> np.ndarray:
+    """pi:[d] -> [N], i.i.d. uniform per coordinate, as int32[d]."""
+    if d < 0 or N <= 0:
+        raise ValueError("need d >= 0 and N > 0")
+    z = splitmix64(seed, d)
+    with np.errstate(over="ignore"):
+        v = ((z >> np.uint64(32)) * np.uint64(N)) >> np.uint64(32)
+    return v.astype(np.int32)
+
+
+@dataclasses.dataclass
+class CSR:
+    """A batch of binary vectors: row r has set indices indices[indptr[r]:indptr[r+1]]."""
+
+    indptr: np.ndarray  # int32[n+1]
+    indices: np.ndarray  # int32[nnz]
+    d: int
+
+    @property
+    def n(self) -> int:
+        return len(self.indptr) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.indptr[-1])
+
+    def row(self, r: int) -> np.ndarray:
+        return self.indices[self.indptr[r]:self.indptr[r + 1]]
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.indptr.astype(np.int64))
+
+    def take(self, rows) -> "CSR":
+        rows = np.asarray(rows, dtype=np.int64)
+        lens = self.lengths()[rows]
+        indptr = np.zeros(len(rows) + 1, dtype=np.int64)
+        np.cumsum(lens, out=indptr[1:])
+        parts = [self.row(int(r)) for r in rows]
+        indices = np.concatenate(parts) if parts else np.zeros(0, np.int32)
+        return CSR(indptr.astype(np.int32), indices.astype(np.int32), self.d)
+
+
+def from_rows(rows, d: int) -> CSR:
+    """CSR from a list of index sequences (kept as given: order, duplicates)."""
+    lens = [len(r) for r in rows]
+    indptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(lens, out=indptr[1:])
+    if indptr[-1] >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 indptr; split the batch")
+    indices = (np.concatenate([np.asarray(r, dtype=np.int64) for r in rows])
+               if rows and indptr[-1] > 0 else np.zeros(0, np.int64))
+    return CSR(indptr.astype(np.int32), indices.astype(np.int32), d)
+
+
+def zipf_truncated_lengths(rng: np.random.Generator, n: int, s: float, lo: int, hi: int) -> np.ndarray:
+    """n draws of P(m) proportional to m^-s on the integers lo..hi."""
+    m = np.arange(lo, hi + 1, dtype=np.float64)
+    cdf = np.cumsum(m ** -s)
+    cdf /= cdf[-1]
+    return (lo + np.searchsorted(cdf, rng.random(n), side="right")).astype(np.int64).clip(lo, hi)
+
+
+def lognormal_lengths(rng: np.random.Generator, n: int, mean: float, sd: float,
+                      lo: int = 1, hi: int | None = None) -> np.ndarray:
+    """Rounded log-normal lengths with the given mean and standard deviation."""
+    sigma2 = math.log1p((sd / mean) ** 2)
+    mu = math.log(mean) - sigma2 / 2
+    x = np.rint(rng.lognormal(mu, math.sqrt(sigma2), n)).astype(np.int64)
+    return x.clip(lo, hi if hi is not None else np.iinfo(np.int64).max)
+
+
+def zipf_rows(rng: np.random.Generator, lengths: np.ndarray, d: int, s: float) -> CSR:
+    """Rows of the given lengths; ids drawn by Zipf(s) popularity without replacement.
+
+    Popularity of rank r (0-based) is proportional to (r+1)^-s; rank r names the
+    id perm[r] for a seeded permutation perm of [0, d). Within a row, draws are
+    taken with replacement and only first occurrences are kept, which is exactly
+    sampling without replacement proportionally to the remaining weights. Each
+    row is returned sorted by id.
+    """
+    lengths = np.asarray(lengths, dtype=np.int64)
+    if (lengths > d).any():
+        raise ValueError("a row cannot hold more than d distinct ids")
+    n = len(lengths)
+    perm = rng.permutation(d).astype(np.int64)
+    cdf = np.cumsum(np.arange(1, d + 1, dtype=np.float64) ** -s)
+    cdf /= cdf[-1]
+
+    chosen = [None] * n
+    draws = [np.zeros(0, np.int64) for _ in range(n)]
+    pending = np.nonzero(lengths > 0)[0]
+    for r in np.nonzero(lengths == 0)[0]:
+        chosen[r] = np.zeros(0, np.int64)
+    factor = 3.0
+    while len(pending):
+        want = np.ceil(lengths[pending] * factor).astype(np.int64) + 16
+        total = int(want.sum())
+        ranks = np.searchsorted(cdf, rng.random(total), side="right").clip(0, d - 1)
+        offs = np.zeros(len(pending) + 1, np.int64)
+        np.cumsum(want, out=offs[1:])
+        still = []
+        for j, r in enumerate(pending):
+            seq = np.concatenate([draws[r], ranks[offs[j]:offs[j + 1]]])
+            _, first = np.unique(seq, return_index=True)
+            if len(first) >= lengths[r]:
+                keep = np.sort(first)[:lengths[r]]
+                chosen[r] = seq[keep]
+                draws[r] = None
+            else:
+                draws[r] = seq
+                still.append(r)
+        pending = np.asarray(still, dtype=np.int64)
+        factor *= 2.0
+    rows = [np.sort(perm[c]) for c in chosen]
+    return from_rows(rows, d)
+
+
+def zipf_rows_fast(rng: np.random.Generator, lengths: np.ndarray, d: int, s: float) -> CSR:
+    """Vectorised form of :func:`zipf_rows` for large corpora (same distribution).
+
+    All rows draw an oversized batch at once; first occurrences are found with
+    one global sort; the few rows left short fall back to :func:`zipf_rows`'s
+    per-row loop, continuing their own draw sequence.
+    """
+    lengths = np.asarray(lengths, dtype=np.int64)
+    if (lengths > d).any():
+        raise ValueError("a row cannot hold more than d distinct ids")
+    n = len(lengths)
+    perm = rng.permutation(d).astype(np.int64)
+    cdf = np.cumsum(np.arange(1, d + 1, dtype=np.float64) ** -s)
+    cdf /= cdf[-1]
+    want = np.ceil(lengths * 3.0).astype(np.int64) + 16
+    want[lengths == 0] = 0
+    offs = np.zeros(n + 1, np.int64)
+    np.cumsum(want, out=offs[1:])
+    total = int(offs[-1])
+    ranks = np.searchsorted(cdf, rng.random(total), side="right").clip(0, d - 1).astype(np.int64)
+    row_of = np.repeat(np.arange(n, dtype=np.int64), want)
+    pos = np.arange(total, dtype=np.int64)
+    key = row_of * d + ranks
+    order = np.lexsort((pos, key))  # by key, then by draw position
+    ks = key[order]
+    is_first = np.ones(total, bool)
+    is_first[1:] = ks[1:] != ks[:-1]
+    fpos = pos[order][is_first]  # draw positions of first occurrences
+    fpos.sort()  # grouped by row (positions are row-contiguous), in draw order
+    frow = row_of[fpos]
+    counts = np.bincount(frow, minlength=n)
+    start = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=start[1:])
+    rank_in_row = np.arange(len(fpos), dtype=np.int64) - start[frow]
+    keep = rank_in_row < lengths[frow]
+    kpos = fpos[keep]
+    krow = row_of[kpos]
+    ids = perm[ranks[kpos]]
+    short = np.nonzero(counts < lengths)[0]
+    # sort ids within rows
+    o = np.lexsort((ids, krow))
+    ids, krow = ids[o], krow[o]
+    got = np.bincount(krow, minlength=n)
+    if len(short):
+        # Continue each short row's own draw sequence until it has enough ids.
+        extra_rng = rng
+        rows_fix = {}
+        for r in short:
+            seq = ranks[offs[r]:offs[r + 1]]
+            while True:
+                _, first = np.unique(seq, return_index=True)
+                if len(first) >= lengths[r]:
+                    break
+                seq = np.concatenate([seq, np.searchsorted(
+                    cdf, extra_rng.random(int(lengths[r]) * 4 + 16), side="right").clip(0, d - 1)])
+            keepi = np.sort(first)[:lengths[r]]
+            rows_fix[int(r)] = np.sort(perm[seq[keepi]])
+        indptr = np.zeros(n + 1, np.int64)
+        np.cumsum(lengths, out=indptr[1:])
+        out = np.empty(int(indptr[-1]), np.int64)
+        gstart = np.zeros(n + 1, np.int64)
+        np.cumsum(got, out=gstart[1:])
+        mask_ok = np.ones(n, bool)
+        mask_ok[short] = False
+        # rows that were complete: copy blocks
+        okrows = np.nonzero(mask_ok & (lengths > 0))[0]
+        src = np.concatenate([np.arange(gstart[r], gstart[r + 1]) for r in okrows]) if len(okrows) else np.zeros(0, np.int64)
+        dst = np.concatenate([np.arange(indptr[r], indptr[r + 1]) for r in okrows]) if len(okrows) else np.zeros(0, np.int64)
+        out[dst] = ids[src]
+        for r, v in rows_fix.items():
+            out[indptr[r]:indptr[r + 1]] = v
+        if indptr[-1] >= 2 ** 31:
+            raise ValueError("nnz does not fit int32 indptr; split the batch")
+        return CSR(indptr.astype(np.int32), out.astype(np.int32), d)
+    indptr = np.zeros(n + 1, np.int64)
+    np.cumsum(got, out=indptr[1:])
+    if indptr[-1] >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 indptr; split the batch")
+    return CSR(indptr.astype(np.int32), ids.astype(np.int32), d)
+
+
+# ---------------------------------------------------------------------------
+# Workload recipes (sizes and distributions of the benchmark workloads)
+# ---------------------------------------------------------------------------
+
+SEED_PI = 0x5EED_B1A5
+SEED_SMALL = 1001
+SEED_CORPUS = 2002
+SEED_QUERIES = 3003
+
+
+def small_corpus(n: int = 1000, d: int = 10_000, seed: int = SEED_SMALL) -> CSR:
+    """n vectors, d dims, lengths Zipf(1.1) truncated to [5, 500], Zipf(1.1) ids."""
+    rng = np.random.default_rng(seed)
+    lengths = zipf_truncated_lengths(rng, n, 1.1, 5, 500)
+    return zipf_rows(rng, lengths, d, 1.1)
+
+
+def lognormal_corpus(n: int, d: int = 100_000, mean: float = 230.0, sd: float = 150.0,
+                     seed: int = SEED_CORPUS, fast: bool = True) -> CSR:
+    """n vectors, d dims, lengths round(lognormal) with the given mean/sd (>= 1)."""
+    rng = np.random.default_rng(seed)
+    lengths = lognormal_lengths(rng, n, mean, sd, lo=1, hi=d)
+    gen = zipf_rows_fast if fast else zipf_rows
+    return gen(rng, lengths, d, 1.1)
+
+
+def planted_pairs(rng: np.random.Generator, base: CSR, frac: np.ndarray, s: float = 1.1) -> CSR:
+    """For each row a of ``base``, a partner b = a with a fraction frac[r] of its ids
+    replaced by fresh Zipf(s)-popular ids not already in a (near-duplicate pairs)."""
+    d = base.d
+    cdf = np.cumsum(np.arange(1, d + 1, dtype=np.float64) ** -s)
+    cdf /= cdf[-1]
+    perm = rng.permutation(d).astype(np.int64)
+    rows = []
+    for r in range(base.n):
+        a = base.row(r).astype(np.int64)
+        m = len(a)
+        nrep = int(round(frac[r] * m))
+        keep = rng.permutation(m)[: m - nrep]
+        cur = set(int(x) for x in a)
+        kept = [int(a[i]) for i in keep]
+        new = []
+        while len(new) < nrep and len(cur) < d:
+            cand = perm[np.searchsorted(cdf, rng.random(2 * nrep + 8), side="right").clip(0, d - 1)]
+            for c in cand:
+                c = int(c)
+                if c not in cur:
+                    cur.add(c)
+                    new.append(c)
+                    if len(new) == nrep:
+                        break
+        rows.append(np.sort(np.asarray(kept + new, dtype=np.int64)))
+    return from_rows(rows, d)
