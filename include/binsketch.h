@@ -1,0 +1,166 @@
+/*
+ * binsketch.h — C ABI of the BinSketch GPU library (libbinsketch.so, gfx950).
+ *
+ * BinSketch (Pratap, Bera, Revanuru, arXiv 1910.04658) compresses a sparse
+ * binary vector a in {0,1}^d into an N-bit sketch a_s by sending every set bit
+ * i through a random map pi:[d] -> [N] and OR-ing the bits that land on the
+ * same target (Section 3, Definition "BinSketch"). Inner product, Hamming
+ * distance, Jaccard and cosine similarity are then estimated from |a_s|,
+ * |b_s| and |a_s AND b_s| alone (Algorithms 1-4).
+ *
+ * Conventions shared by every entry point
+ *   - All data pointers are DEVICE pointers on the current HIP device,
+ *     allocated and owned by the caller. The library allocates nothing and
+ *     keeps no state between calls apart from a per-device check that the
+ *     device is a gfx950.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on that stream and returns before the
+ *     work completes; results are valid once the stream has been synchronised.
+ *   - Indices are 0-based (the paper counts from 1).
+ *   - A sketch of width N is N/64 little-endian 64-bit words per row; bit j of
+ *     the sketch is bit (j % 64) of word (j / 64). N must be a multiple of 64,
+ *     between 64 and 65536.
+ *   - Errors that the host can see from the arguments alone are returned as a
+ *     bs_status before anything is enqueued, and no output is written. Errors
+ *     in the CONTENT of device arrays (an index outside [0, d), a map value
+ *     outside [0, N), a malformed indptr) cannot be seen by the host without
+ *     a synchronisation; bs_sketch reports them through `err_flag`.
+ *   - Every call may be captured into a HIP graph: none of them allocates,
+ *     synchronises or issues a memset node.
+ */
+#ifndef BINSKETCH_H
+#define BINSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BS_OK = 0,
+  BS_ERR_NULL = 1,      /* a required pointer is NULL */
+  BS_ERR_ARG = 2,       /* a size or parameter is out of range */
+  BS_ERR_WORKSPACE = 3, /* the workspace is NULL or smaller than required */
+  BS_ERR_HIP = 4,       /* the HIP runtime rejected a launch */
+  BS_ERR_DEVICE = 5     /* the current device is not a gfx950 */
+} bs_status;
+
+typedef enum { BS_IP = 0, BS_HAMMING = 1, BS_JACCARD = 2, BS_COSINE = 3 } bs_measure;
+
+/* Bits that bs_sketch ORs into *err_flag. */
+#define BS_FLAG_INDPTR 1 /* indptr[0] != 0, not non-decreasing, or beyond nnz */
+#define BS_FLAG_INDEX 2  /* a CSR index outside [0, d) */
+#define BS_FLAG_MAP 4    /* a value of pi outside [0, N) */
+
+#define BS_MAX_N 65536
+#define BS_MAX_K 1024
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int bs_version(void);
+
+/* Human-readable name of a bs_status value (static storage). */
+const char* bs_status_string(int status);
+
+/* Number of 64-bit words per sketch, N/64; 0 if N is not a valid width. */
+int32_t bs_words(int32_t N);
+
+/*
+ * bs_sketch — compress n_rows binary vectors (Section 3, Definition
+ * "BinSketch"): sketches[r] has bit j set iff some index i of row r has
+ * pi[i] == j; popcounts[r] = |a_s| (Algorithm 1, first step).
+ *
+ *   indptr     int32[n_rows + 1]  CSR row pointers: row r holds
+ *                                 indices[indptr[r] .. indptr[r+1]). Must
+ *                                 start at 0, be non-decreasing and end at nnz.
+ *   indices    int32[nnz]         set indices in [0, d); any order, repeats
+ *                                 allowed (the vectors are binary).
+ *   n_rows     >= 0               number of vectors.
+ *   nnz        >= 0, < 2^31       length of `indices` (the int32 indptr
+ *                                 bounds a batch to 2^31-1 set bits).
+ *   pi         int32[d]           the random map, values in [0, N).
+ *   d          >= 1, < 2^31       dimension of the input vectors.
+ *   N                              sketch width in bits (see above).
+ *   sketches   uint64[n_rows][N/64] output; every word is written.
+ *   popcounts  int32[n_rows]      output, or NULL to skip.
+ *   err_flag   int32[1]           device word that receives BS_FLAG_* bits by
+ *                                 atomic OR when the content is malformed, or
+ *                                 NULL. The caller clears it; it is never
+ *                                 cleared here. When a flag is raised the
+ *                                 affected rows are written but undefined.
+ * Returns BS_ERR_ARG for a bad size or width, then BS_ERR_NULL for a NULL
+ * indptr or pi, a NULL indices with nnz > 0 or a NULL sketches with
+ * n_rows > 0 (a pointer to an empty array may be NULL everywhere below).
+ */
+bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_rows, int64_t nnz,
+                    const int32_t* pi, int64_t d, int32_t N, uint64_t* sketches,
+                    int32_t* popcounts, int32_t* err_flag, void* stream);
+
+/*
+ * bs_and_popcount — all-pairs sketch inner products
+ * out[p][q] = |A_p AND B_q| = <a_s, b_s> (Algorithm 1, second step).
+ *
+ *   A   uint64[nA][N/64], B uint64[nB][N/64]   sketches (as bs_sketch writes).
+ *   out int32[nA][nB]                          output, row-major.
+ * nA, nB >= 0 with nA * nB < 2^62.
+ */
+bs_status bs_and_popcount(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB,
+                          int32_t N, int32_t* out, void* stream);
+
+/*
+ * bs_estimate — all-pairs estimates in FP64 (Algorithms 1-4) for every pair
+ * (A_p, B_q), written row-major [nA][nB] into each non-NULL output:
+ *   ip   estimated inner product n_ab            (Algorithm 1)
+ *   ham  estimated Hamming distance              (Algorithm 2)
+ *   js   estimated Jaccard similarity            (Algorithm 3)
+ *   cos  estimated cosine similarity             (Algorithm 4)
+ * At least one output must be non-NULL. The estimators are evaluated as
+ *   T(x) = ln(1 - x/N) / ln(1 - 1/N),   x clamped to N-1 (saturation),
+ *   s = T(|a_s|) + T(|b_s|),  ip = s - T(|a_s OR b_s|),  ham = s - 2 ip,
+ *   js = ip / (ip + ham) (0 when the denominator is 0),
+ *   cos = ip / sqrt(T(|a_s|) T(|b_s|)) (0 when the product is 0),
+ * which equals Algorithm 1 exactly whenever no count reaches N, with
+ * Hamming read as |a| + |b| - 2 IP (the number of differing coordinates).
+ * Negative estimates are returned unclamped.
+ *   workspace  device buffer of at least bs_estimate_workspace_size(nA, nB, N)
+ *              bytes, 256-byte aligned; overwritten (the T table and the row
+ *              popcounts |a_s|, |b_s| of Algorithm 1, first step).
+ */
+size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N);
+bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB, int32_t N,
+                      double* ip, double* ham, double* js, double* cos, void* workspace,
+                      size_t workspace_bytes, void* stream);
+
+/*
+ * bs_topk — for every query row Q_p, the k corpus rows C_q with the best
+ * FP32 score of `measure` (the estimators of bs_estimate evaluated in IEEE
+ * float from T rounded to float): highest first for BS_IP, BS_JACCARD and
+ * BS_COSINE, lowest first for BS_HAMMING; ties go to the smaller corpus index.
+ *
+ *   Q          uint64[nQ][N/64] query sketches;  C uint64[nC][N/64] corpus.
+ *   k          1 <= k <= min(nC, BS_MAX_K).
+ *   out_idx    int32[nQ][k]   corpus row indices, best first.
+ *   out_score  float[nQ][k]   their scores, or NULL to skip.
+ *   workspace  >= bs_topk_workspace_size(nQ, nC, N, k) bytes, 256-byte
+ *              aligned, overwritten.
+ * The result does not depend on the launch configuration or on timing.
+ */
+size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int32_t k);
+bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, int64_t nC, int32_t N,
+                  int32_t measure, int32_t k, int32_t* out_idx, float* out_score,
+                  void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Testing hook, not for production callers: caps the per-query candidate
+ * list of bs_topk at `cap` entries (0 restores the automatic size) so that
+ * tests can drive the overflow path, which must return the same result.
+ * Process-wide; not thread-safe. Always returns 0.
+ */
+int bs_debug_set_topk_capacity(int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BINSKETCH_H */

@@ -1,0 +1,220 @@
+"""Thin ctypes binding of libbinsketch.so (the C ABI in include/binsketch.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of the library. Tensors must live on the current CUDA/HIP device;
+calls are enqueued on torch's current stream and return before completion,
+like the C functions. Sketches are carried in int64 tensors (bit-identical to
+the library's uint64 words).
+
+If the shared library is missing, every call raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libbinsketch.so")
+
+BS_OK, BS_ERR_NULL, BS_ERR_ARG, BS_ERR_WORKSPACE, BS_ERR_HIP, BS_ERR_DEVICE = range(6)
+BS_IP, BS_HAMMING, BS_JACCARD, BS_COSINE = range(4)
+FLAG_INDPTR, FLAG_INDEX, FLAG_MAP = 1, 2, 4
+MEASURES = {"ip": BS_IP, "ham": BS_HAMMING, "hamming": BS_HAMMING, "js": BS_JACCARD,
+            "jaccard": BS_JACCARD, "cos": BS_COSINE, "cosine": BS_COSINE}
+
+_lock = threading.Lock()
+_lib = None
+
+
+class BinSketchError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s failed: %s (status %d)" % (where, status_string(status), status))
+
+
+def load():
+    """Load libbinsketch.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libbinsketch.so is not built: run __graft_entry__.build() "
+                                   "or python paper_1910_04658_amd/build.py")
+            L = ctypes.CDLL(LIB_PATH)
+            p, i64, i32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t
+            L.bs_version.restype = ctypes.c_int
+            L.bs_status_string.argtypes = [ctypes.c_int]
+            L.bs_status_string.restype = ctypes.c_char_p
+            L.bs_words.argtypes = [i32]
+            L.bs_words.restype = i32
+            L.bs_sketch.argtypes = [p, p, i64, i64, p, i64, i32, p, p, p, p]
+            L.bs_sketch.restype = ctypes.c_int
+            L.bs_and_popcount.argtypes = [p, i64, p, i64, i32, p, p]
+            L.bs_and_popcount.restype = ctypes.c_int
+            L.bs_estimate_workspace_size.argtypes = [i64, i64, i32]
+            L.bs_estimate_workspace_size.restype = sz
+            L.bs_estimate.argtypes = [p, i64, p, i64, i32, p, p, p, p, p, sz, p]
+            L.bs_estimate.restype = ctypes.c_int
+            L.bs_topk_workspace_size.argtypes = [i64, i64, i32, i32]
+            L.bs_topk_workspace_size.restype = sz
+            L.bs_topk.argtypes = [p, i64, p, i64, i32, i32, i32, p, p, p, sz, p]
+            L.bs_topk.restype = ctypes.c_int
+            L.bs_debug_set_topk_capacity.argtypes = [i64]
+            L.bs_debug_set_topk_capacity.restype = ctypes.c_int
+            _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    return load().bs_status_string(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != BS_OK:
+        raise BinSketchError(status, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t: torch.Tensor, name: str, dtype, ndim=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError("%s must have %d dims" % (name, ndim))
+    return t
+
+
+def words(N: int) -> int:
+    return int(load().bs_words(int(N)))
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    ws = torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + max(int(nbytes), 256)]
+
+
+def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int,
+           out: torch.Tensor | None = None, popcounts: bool | torch.Tensor = True,
+           err_flag: torch.Tensor | None = None):
+    """bs_sketch: (sketches int64[n][N/64], popcounts int32[n] or None)."""
+    _need(indptr, "indptr", torch.int32, 1)
+    _need(indices, "indices", torch.int32, 1)
+    _need(pi, "pi", torch.int32, 1)
+    n = indptr.numel() - 1
+    if n < 0:
+        raise ValueError("indptr must hold n_rows + 1 entries")
+    W = words(N)
+    if W == 0:
+        raise ValueError("invalid sketch width N=%d" % N)
+    dev = indptr.device
+    if out is None:
+        out = torch.empty((n, W), dtype=torch.int64, device=dev)
+    else:
+        _need(out, "out", torch.int64, 2)
+        if tuple(out.shape) != (n, W):
+            raise ValueError("out must be [n_rows][N/64]")
+    pop = None
+    if isinstance(popcounts, torch.Tensor):
+        pop = _need(popcounts, "popcounts", torch.int32, 1)
+        if pop.numel() != n:
+            raise ValueError("popcounts must have n_rows entries")
+    elif popcounts:
+        pop = torch.empty(n, dtype=torch.int32, device=dev)
+    if err_flag is not None:
+        _need(err_flag, "err_flag", torch.int32)
+    st = load().bs_sketch(_ptr(indptr), _ptr(indices if indices.numel() else None), n, indices.numel(),
+                          _ptr(pi), pi.numel(), int(N), _ptr(out), _ptr(pop), _ptr(err_flag), _stream())
+    _check(st, "bs_sketch")
+    return out, pop
+
+
+def and_popcount(A: torch.Tensor, B: torch.Tensor, N: int, out: torch.Tensor | None = None):
+    """bs_and_popcount: int32[nA][nB] of |A_p AND B_q|."""
+    W = words(N)
+    _need(A, "A", torch.int64, 2)
+    _need(B, "B", torch.int64, 2)
+    if A.shape[1] != W or B.shape[1] != W:
+        raise ValueError("sketch rows must hold N/64 words")
+    if out is None:
+        out = torch.empty((A.shape[0], B.shape[0]), dtype=torch.int32, device=A.device)
+    else:
+        _need(out, "out", torch.int32, 2)
+    st = load().bs_and_popcount(_ptr(A), A.shape[0], _ptr(B), B.shape[0], int(N), _ptr(out), _stream())
+    _check(st, "bs_and_popcount")
+    return out
+
+
+def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "js", "cos"),
+             workspace: torch.Tensor | None = None):
+    """bs_estimate: dict measure -> float64[nA][nB]."""
+    W = words(N)
+    _need(A, "A", torch.int64, 2)
+    _need(B, "B", torch.int64, 2)
+    if A.shape[1] != W or B.shape[1] != W:
+        raise ValueError("sketch rows must hold N/64 words")
+    nA, nB = A.shape[0], B.shape[0]
+    outs = {}
+    for m in measures:
+        key = {"ip": "ip", "ham": "ham", "hamming": "ham", "js": "js", "jaccard": "js",
+               "cos": "cos", "cosine": "cos"}[m]
+        outs[key] = torch.empty((nA, nB), dtype=torch.float64, device=A.device)
+    L = load()
+    need = L.bs_estimate_workspace_size(nA, nB, int(N))
+    if workspace is None:
+        workspace = _workspace(need, A.device)
+    st = L.bs_estimate(_ptr(A), nA, _ptr(B), nB, int(N), _ptr(outs.get("ip")), _ptr(outs.get("ham")),
+                       _ptr(outs.get("js")), _ptr(outs.get("cos")), _ptr(workspace), workspace.numel(),
+                       _stream())
+    _check(st, "bs_estimate")
+    return outs
+
+
+def topk_workspace_size(nQ: int, nC: int, N: int, k: int) -> int:
+    return int(load().bs_topk_workspace_size(int(nQ), int(nC), int(N), int(k)))
+
+
+def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool = True,
+         workspace: torch.Tensor | None = None, out_idx: torch.Tensor | None = None,
+         out_score: torch.Tensor | None = None):
+    """bs_topk: (idx int32[nQ][k], score float32[nQ][k] or None)."""
+    m = MEASURES[measure] if isinstance(measure, str) else int(measure)
+    W = words(N)
+    _need(Q, "Q", torch.int64, 2)
+    _need(C, "C", torch.int64, 2)
+    if Q.shape[1] != W or C.shape[1] != W:
+        raise ValueError("sketch rows must hold N/64 words")
+    nQ, nC = Q.shape[0], C.shape[0]
+    if out_idx is None:
+        out_idx = torch.empty((nQ, k), dtype=torch.int32, device=Q.device)
+    if out_score is None and scores:
+        out_score = torch.empty((nQ, k), dtype=torch.float32, device=Q.device)
+    L = load()
+    need = L.bs_topk_workspace_size(nQ, nC, int(N), int(k))
+    if need == 0:
+        raise ValueError("invalid top-k arguments (nC=%d, N=%d, k=%d)" % (nC, N, k))
+    if workspace is None:
+        workspace = _workspace(need, Q.device)
+    st = L.bs_topk(_ptr(Q), nQ, _ptr(C), nC, int(N), m, int(k), _ptr(out_idx), _ptr(out_score),
+                   _ptr(workspace), workspace.numel(), _stream())
+    _check(st, "bs_topk")
+    return out_idx, out_score
+
+
+def debug_set_topk_capacity(cap: int):
+    load().bs_debug_set_topk_capacity(int(cap))

@@ -1,0 +1,57 @@
+// Internal helpers shared by the library's HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "binsketch.h"
+
+namespace bs {
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// Returns BS_OK if the current device is a gfx950, else BS_ERR_DEVICE.
+bs_status check_device();
+
+inline bool valid_width(int32_t N) { return N >= 64 && N <= BS_MAX_N && N % 64 == 0; }
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bs_status launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? BS_OK : BS_ERR_HIP;
+}
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---- device helpers -------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// View of read-only global data through the constant address space, so that
+// wave-uniform loads from it become scalar (s_load) loads feeding SGPR
+// operands. Only for data no kernel writes while the reading kernel runs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+
+__device__ __forceinline__ uint32_t popc32(uint32_t x) { return __builtin_popcount(x); }
+
+// Order-preserving map float -> uint32 (larger float -> larger key). -0.0 is
+// first turned into +0.0 so that the two zeros compare equal, as IEEE says.
+__device__ __forceinline__ uint32_t float_key(float f) {
+  f = f + 0.0f;
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float key_float(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  return __uint_as_float(u);
+}
+
+}  // namespace bs

@@ -1,0 +1,257 @@
+// All-pairs sketch inner products and estimates on gfx950.
+//
+// <a_s, b_s> = |a_s AND b_s| (Algorithm 1, second step) is bit work, not a
+// floating-point contraction, so it runs on the vector ALU: per 32-bit word
+// pair one v_and_b32 and one v_bcnt_u32_b32 (which also accumulates).
+//
+// Mapping: one lane per B row, whose words sit in VGPRs; the A rows are
+// wave-uniform, so their words are fetched by the scalar unit (s_load) and
+// feed the VALU as SGPR operands at no vector-memory or LDS cost. Lanes of a
+// wave hold consecutive B rows, so every output row segment is a coalesced
+// 64-lane store.
+//
+// Estimator epilogue (Algorithms 1-4, canonical form): with
+// T(x) = ln(1 - x/N) / ln(1 - 1/N) tabulated for x = 0..N (T(N) := T(N-1),
+// the saturation clamp), and x_u = x_a + x_b - x_ab = |a_s OR b_s|,
+//   s = T(x_a) + T(x_b),  ip = s - T(x_u),  ham = s - 2 ip,
+//   js = ip / (ip + ham),  cos = ip / sqrt(T(x_a) T(x_b)).
+#include "bs_common.h"
+
+namespace bs {
+
+// T(x) for x in [0, N] in FP64 and FP32 (the FP32 table is the FP64 value
+// rounded once). Both forms log1p(-x/N) and log(1-x/N) take the logarithm of
+// the same exactly representable number when N is a power of two.
+__global__ void build_lut_kernel(int32_t N, double* __restrict__ t64, float* __restrict__ t32) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x > N) return;
+  const int xc = x < N ? x : N - 1;
+  const double v = xc == 0 ? 0.0 : log1p(-(double)xc / (double)N) / log1p(-1.0 / (double)N);
+  if (t64) t64[x] = v;
+  if (t32) t32[x] = (float)v;
+}
+
+// popcount of each row of X[n][W32] (32-bit words).
+__global__ void row_popcount_kernel(const uint32_t* __restrict__ X, int64_t n, int32_t W32,
+                                    int32_t* __restrict__ pop) {
+  // one wave per row: lanes sum strided words, then a wave reduction
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (row >= n) return;
+  const uint32_t* x = X + (size_t)row * W32;
+  uint32_t c = 0;
+  for (int w = lane; w < W32; w += kWave) c += popc32(x[w]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if (lane == 0) pop[row] = (int32_t)c;
+}
+
+void launch_lut(int32_t N, double* t64, float* t32, hipStream_t s) {
+  const int threads = 256;
+  hipLaunchKernelGGL(build_lut_kernel, dim3((N + 1 + threads - 1) / threads), dim3(threads), 0, s, N,
+                     t64, t32);
+}
+
+void launch_row_popcount(const uint64_t* X, int64_t n, int32_t N, int32_t* pop, hipStream_t s) {
+  if (n <= 0) return;
+  const int rows_per_block = 4;
+  hipLaunchKernelGGL(row_popcount_kernel, dim3((unsigned)((n + rows_per_block - 1) / rows_per_block)),
+                     dim3(rows_per_block * kWave), 0, s, reinterpret_cast<const uint32_t*>(X), n, N / 32,
+                     pop);
+}
+
+namespace {
+
+constexpr int kPairThreads = 256;
+
+struct DenseArgs {
+  const uint32_t* __restrict__ A;  // [nA][W32]
+  const uint32_t* __restrict__ B;  // [nB][W32]
+  const int32_t* __restrict__ popA;
+  const int32_t* __restrict__ popB;
+  const double* __restrict__ t64;  // T(0..N)
+  int32_t* __restrict__ xab_out;   // [nA][nB] (mode 0)
+  double* __restrict__ ip;         // [nA][nB] (mode 1), each may be null
+  double* __restrict__ ham;
+  double* __restrict__ js;
+  double* __restrict__ cs;
+  int64_t nA, nB;
+  int32_t W32;
+  int32_t a_per_block;
+};
+
+// WC: 32-bit words of B held in VGPRs per chunk; TA: A rows per tile.
+template <int WC, int TA, bool EST>
+__global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
+  const int64_t b = (int64_t)blockIdx.x * kPairThreads + threadIdx.x;
+  const bool b_ok = b < a.nB;
+  const int64_t bb = b_ok ? b : a.nB - 1;
+  const int64_t a_begin = (int64_t)blockIdx.y * a.a_per_block;
+  if (a_begin >= a.nA) return;
+  const int64_t a_end = a_begin + a.a_per_block < a.nA ? a_begin + a.a_per_block : a.nA;
+  const int W32 = a.W32;
+  const int nchunks = W32 / WC;
+  const uint32_t* brow = a.B + (size_t)bb * W32;
+
+  double Tb = 0.0;
+  int32_t xb = 0;
+  if (EST) {
+    xb = a.popB[bb];
+    Tb = a.t64[xb];
+  }
+
+  uint32_t bw[WC];
+  if (nchunks == 1) {
+#pragma unroll
+    for (int w = 0; w < WC; ++w) bw[w] = brow[w];
+  }
+  for (int64_t a0 = a_begin; a0 < a_end; a0 += TA) {
+    uint32_t acc[TA];
+#pragma unroll
+    for (int t = 0; t < TA; ++t) acc[t] = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      if (nchunks != 1) {
+#pragma unroll
+        for (int w = 0; w < WC; ++w) bw[w] = brow[c * WC + w];
+      }
+#pragma unroll
+      for (int t = 0; t < TA; ++t) {
+        const int64_t ar = (a0 + t < a_end) ? a0 + t : a_end - 1;
+        const cptr<uint32_t> arow = as_const(a.A + (size_t)ar * W32 + c * WC);
+#pragma unroll
+        for (int w = 0; w < WC; ++w) acc[t] += popc32(arow[w] & bw[w]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TA; ++t) {
+      const int64_t ar = a0 + t;
+      if (ar >= a_end || !b_ok) continue;
+      const size_t o = (size_t)ar * a.nB + b;
+      if (!EST) {
+        __builtin_nontemporal_store((int32_t)acc[t], a.xab_out + o);
+      } else {
+        const int32_t xa = as_const(a.popA)[ar];
+        const double Ta = a.t64[xa];
+        const double Tu = a.t64[xa + xb - (int32_t)acc[t]];
+        const double s = Ta + Tb;
+        const double ip = s - Tu;
+        const double ham = s - 2.0 * ip;
+        if (a.ip) __builtin_nontemporal_store(ip, a.ip + o);
+        if (a.ham) __builtin_nontemporal_store(ham, a.ham + o);
+        if (a.js) {
+          const double den = ip + ham;
+          __builtin_nontemporal_store(den == 0.0 ? 0.0 : ip / den, a.js + o);
+        }
+        if (a.cs) {
+          const double pr = Ta * Tb;
+          __builtin_nontemporal_store(pr == 0.0 ? 0.0 : ip / sqrt(pr), a.cs + o);
+        }
+      }
+    }
+  }
+}
+
+template <bool EST>
+bs_status launch_dense(DenseArgs a, hipStream_t s) {
+  const int W32 = a.W32;
+  // Largest power of two <= 64 that divides W32 (W32 is even).
+  int WC = 64;
+  while (W32 % WC) WC >>= 1;
+  const int64_t bblocks = (a.nB + kPairThreads - 1) / kPairThreads;
+  // Enough blocks to fill 256 CUs several times over; A tile rows multiple of 4.
+  int64_t per = (a.nA * bblocks + 4095) / 4096;
+  per = per < 4 ? 4 : (per > 256 ? 256 : per);
+  per = (per + 3) / 4 * 4;
+  a.a_per_block = (int32_t)per;
+  const int64_t ablocks = (a.nA + per - 1) / per;
+  if (bblocks > INT32_MAX || ablocks > 65535) return BS_ERR_ARG;
+  dim3 grid((unsigned)bblocks, (unsigned)ablocks);
+  dim3 block(kPairThreads);
+#define BS_DENSE_CASE(wc, ta)                                                          \
+  case wc:                                                                             \
+    hipLaunchKernelGGL((pair_dense_kernel<wc, ta, EST>), grid, block, 0, s, a); \
+    break;
+  switch (WC) {
+    BS_DENSE_CASE(2, 4)
+    BS_DENSE_CASE(4, 4)
+    BS_DENSE_CASE(8, 4)
+    BS_DENSE_CASE(16, 4)
+    BS_DENSE_CASE(32, 4)
+    BS_DENSE_CASE(64, 4)
+    default:
+      return BS_ERR_ARG;
+  }
+#undef BS_DENSE_CASE
+  return launch_status();
+}
+
+}  // namespace
+}  // namespace bs
+
+extern "C" bs_status bs_and_popcount(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB,
+                                     int32_t N, int32_t* out, void* stream) {
+  using namespace bs;
+  if (nA < 0 || nB < 0 || !valid_width(N)) return BS_ERR_ARG;
+  if ((!A && nA > 0) || (!B && nB > 0) || (!out && nA > 0 && nB > 0)) return BS_ERR_NULL;
+  if (nA > 0 && nB > (INT64_C(1) << 62) / nA) return BS_ERR_ARG;
+  bs_status st = check_device();
+  if (st != BS_OK) return st;
+  if (nA == 0 || nB == 0) return BS_OK;
+  DenseArgs a = {};
+  a.A = reinterpret_cast<const uint32_t*>(A);
+  a.B = reinterpret_cast<const uint32_t*>(B);
+  a.xab_out = out;
+  a.nA = nA;
+  a.nB = nB;
+  a.W32 = N / 32;
+  return launch_dense<false>(a, as_stream(stream));
+}
+
+extern "C" size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N) {
+  using namespace bs;
+  if (!valid_width(N) || nA < 0 || nB < 0) return 0;
+  return align256((size_t)(N + 1) * sizeof(double)) + align256((size_t)nA * 4) +
+         align256((size_t)nB * 4);
+}
+
+extern "C" bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB,
+                                 int32_t N, double* ip, double* ham, double* js, double* cos,
+                                 void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace bs;
+  if (nA < 0 || nB < 0 || !valid_width(N)) return BS_ERR_ARG;
+  if ((!A && nA > 0) || (!B && nB > 0)) return BS_ERR_NULL;
+  if (!ip && !ham && !js && !cos) return BS_ERR_NULL;
+  if (nA > 0 && nB > (INT64_C(1) << 62) / nA) return BS_ERR_ARG;
+  const size_t need = bs_estimate_workspace_size(nA, nB, N);
+  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return BS_ERR_WORKSPACE;
+  bs_status st = check_device();
+  if (st != BS_OK) return st;
+  if (nA == 0 || nB == 0) return BS_OK;
+  char* ws = static_cast<char*>(workspace);
+  double* t64 = reinterpret_cast<double*>(ws);
+  ws += align256((size_t)(N + 1) * sizeof(double));
+  int32_t* popA = reinterpret_cast<int32_t*>(ws);
+  ws += align256((size_t)nA * 4);
+  int32_t* popB = reinterpret_cast<int32_t*>(ws);
+  hipStream_t s = as_stream(stream);
+  launch_lut(N, t64, nullptr, s);
+  launch_row_popcount(A, nA, N, popA, s);
+  launch_row_popcount(B, nB, N, popB, s);
+  st = launch_status();
+  if (st != BS_OK) return st;
+  DenseArgs a = {};
+  a.A = reinterpret_cast<const uint32_t*>(A);
+  a.B = reinterpret_cast<const uint32_t*>(B);
+  a.popA = popA;
+  a.popB = popB;
+  a.t64 = t64;
+  a.ip = ip;
+  a.ham = ham;
+  a.js = js;
+  a.cs = cos;
+  a.nA = nA;
+  a.nB = nB;
+  a.W32 = N / 32;
+  return launch_dense<true>(a, s);
+}

@@ -27,3 +27,13 @@ def dev():
     if not torch.cuda.is_available():
         pytest.fail("GPU test run without a visible GPU")
     return torch.device("cuda:0")
+
+
+_DATA = {}
+
+
+def shared_input(key, make):
+    """Session-wide cache of generated inputs (the large ones take seconds)."""
+    if key not in _DATA:
+        _DATA[key] = make()
+    return _DATA[key]

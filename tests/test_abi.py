@@ -1,0 +1,98 @@
+"""The C ABI: the library loads, exports every function include/binsketch.h
+declares, and rejects bad arguments on the host before any launch (these
+calls return before touching a device, so they run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "binsketch.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1910_04658_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_1910_04658_amd import build
+        build.build()
+    return binding.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(bs_[a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ["bs_sketch", "bs_and_popcount", "bs_estimate", "bs_estimate_workspace_size", "bs_topk",
+              "bs_topk_workspace_size", "bs_words", "bs_status_string", "bs_version"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for n in declared_functions():
+        assert hasattr(lib, n), "libbinsketch.so does not export %s" % n
+
+
+def test_words_and_status(lib):
+    assert lib.bs_words(1024) == 16
+    assert lib.bs_words(64) == 1
+    assert lib.bs_words(65536) == 1024
+    for bad in [0, 32, 100, 65600, -64]:
+        assert lib.bs_words(bad) == 0
+    assert lib.bs_status_string(0) == b"ok"
+    assert lib.bs_version() >= 10000
+
+
+P = ctypes.c_void_p
+FAKE = P(0x1000)  # never dereferenced: every call below fails host-side validation
+
+
+def test_sketch_rejects_bad_arguments(lib):
+    s = lib.bs_sketch
+    assert s(None, FAKE, 1, 1, FAKE, 10, 64, FAKE, None, None, None) == 1
+    assert s(FAKE, None, 1, 5, FAKE, 10, 64, FAKE, None, None, None) == 1
+    assert s(FAKE, FAKE, 1, 1, None, 10, 64, FAKE, None, None, None) == 1
+    assert s(FAKE, FAKE, 1, 1, FAKE, 10, 64, None, None, None, None) == 1
+    assert s(FAKE, FAKE, -1, 1, FAKE, 10, 64, FAKE, None, None, None) == 2
+    assert s(FAKE, FAKE, 1, -1, FAKE, 10, 64, FAKE, None, None, None) == 2
+    assert s(FAKE, FAKE, 1, 2 ** 31, FAKE, 10, 64, FAKE, None, None, None) == 2
+    assert s(FAKE, FAKE, 1, 1, FAKE, 0, 64, FAKE, None, None, None) == 2
+    for N in [0, 63, 100, 65536 + 64]:
+        assert s(FAKE, FAKE, 1, 1, FAKE, 10, N, FAKE, None, None, None) == 2
+
+
+def test_pairs_reject_bad_arguments(lib):
+    assert lib.bs_and_popcount(None, 1, FAKE, 1, 64, FAKE, None) == 1
+    assert lib.bs_and_popcount(FAKE, -1, FAKE, 1, 64, FAKE, None) == 2
+    assert lib.bs_and_popcount(FAKE, 1, FAKE, 1, 96, FAKE, None) == 2
+    assert lib.bs_and_popcount(FAKE, 2 ** 40, FAKE, 2 ** 40, 64, FAKE, None) == 2
+    # estimate: no output requested, bad width, missing or short workspace
+    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, None, None, None, None, FAKE, 1 << 20, None) == 1
+    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 65, FAKE, None, None, None, FAKE, 1 << 20, None) == 2
+    need = lib.bs_estimate_workspace_size(1, 1, 64)
+    assert need > 0
+    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, None, need, None) == 3
+    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, FAKE, need - 1, None) == 3
+    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, P(0x1001), need, None) == 3
+
+
+def test_topk_rejects_bad_arguments(lib):
+    t = lib.bs_topk
+    need = lib.bs_topk_workspace_size(10, 100, 256, 5)
+    assert need > 0
+    assert t(None, 10, FAKE, 100, 256, 2, 5, FAKE, None, FAKE, need, None) == 1
+    assert t(FAKE, 10, FAKE, 100, 256, 2, 5, None, None, FAKE, need, None) == 1
+    assert t(FAKE, 10, FAKE, 100, 256, 2, 0, FAKE, None, FAKE, need, None) == 2     # k = 0
+    assert t(FAKE, 10, FAKE, 100, 256, 2, 101, FAKE, None, FAKE, need, None) == 2   # k > nC
+    assert t(FAKE, 10, FAKE, 5000, 256, 2, 1025, FAKE, None, FAKE, need, None) == 2  # k > max
+    assert t(FAKE, 10, FAKE, 100, 256, 4, 5, FAKE, None, FAKE, need, None) == 2     # measure
+    assert t(FAKE, 10, FAKE, 0, 256, 2, 5, FAKE, None, FAKE, need, None) == 2       # empty corpus
+    assert t(FAKE, 10, FAKE, 100, 256, 2, 5, FAKE, None, FAKE, need - 1, None) == 3
+    assert lib.bs_topk_workspace_size(10, 100, 256, 101) == 0
+    assert lib.bs_topk_workspace_size(10, 100, 100, 5) == 0

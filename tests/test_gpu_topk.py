@@ -1,0 +1,124 @@
+"""bs_topk against the CPU oracle's full sort: identical indices and FP32
+scores (both sides rank by the same FP32 evaluation of the estimators)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from helpers import assert_topk_equal, sets_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MEASURES = [oracle.IP, oracle.HAM, oracle.JS, oracle.COS]
+
+
+def sketch_both(c, N, seed, dev):
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    pi = datagen.random_map(c.d, N, seed)
+    w, _ = bs.sketch(to_dev(c.indptr, dev), to_dev(c.indices, dev), to_dev(pi, dev), N)
+    torch.cuda.synchronize()
+    return w, oracle.sketch_sets(c.indptr, c.indices, c.d, pi, N)
+
+
+def gpu_topk(Q, C, N, m, k):
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    i, s = bs.topk(Q, C, N, m, k)
+    torch.cuda.synchronize()
+    return i.cpu().numpy(), s.cpu().numpy()
+
+
+@pytest.mark.parametrize("m", MEASURES)
+def test_corpus_inside_the_sample(m, dev):
+    """nC <= 4096: the sample pass covers the whole corpus."""
+    c = datagen.small_corpus(n=1000, d=10000, seed=21)
+    w, S = sketch_both(c, 1024, 5, dev)
+    q = np.arange(0, 1000, 7)
+    gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 1024, m, 25)
+    oi, osc = oracle.topk(sets_rows(S, q), S, 1024, m, 25)
+    assert_topk_equal(gi, gs, oi, osc)
+
+
+@pytest.mark.parametrize("m", MEASURES)
+@pytest.mark.parametrize("N,k", [(256, 1), (256, 100), (1024, 37), (4096, 100)])
+def test_scan_path(m, N, k, dev):
+    """nC > 4096: sample, filtered scan and selection."""
+    c = datagen.lognormal_corpus(20011, d=30000, seed=22)
+    w, S = sketch_both(c, N, 6, dev)
+    q = np.arange(0, 20011, 401)
+    gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, N, m, k)
+    oi, osc = oracle.topk(sets_rows(S, q), S, N, m, k)
+    assert_topk_equal(gi, gs, oi, osc)
+
+
+@pytest.mark.parametrize("m", [oracle.JS, oracle.HAM])
+def test_overflow_fallback_path(m, dev):
+    """A candidate capacity of exactly the sample size forces every query onto
+    the whole-corpus fallback; the result must not change."""
+    from paper_1910_04658_amd import binding as bs
+    c = datagen.lognormal_corpus(9000, d=20000, seed=23)
+    w, S = sketch_both(c, 512, 7, dev)
+    q = np.arange(0, 9000, 450)
+    try:
+        bs.debug_set_topk_capacity(4096)
+        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 512, m, 50)
+    finally:
+        bs.debug_set_topk_capacity(0)
+    oi, osc = oracle.topk(sets_rows(S, q), S, 512, m, 50)
+    assert_topk_equal(gi, gs, oi, osc)
+
+
+def test_exact_ties_break_by_index(dev):
+    """Many identical corpus rows: equal scores, ordered by smaller index."""
+    base = datagen.small_corpus(n=50, d=4000, seed=24)
+    rows = [base.row(r % 50).tolist() for r in range(6000)]
+    c = datagen.from_rows(rows, base.d)
+    w, S = sketch_both(c, 256, 8, dev)
+    q = np.arange(0, 50, 5)
+    for m in MEASURES:
+        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 256, m, 200)
+        oi, osc = oracle.topk(sets_rows(S, q), S, 256, m, 200)
+        assert_topk_equal(gi, gs, oi, osc)
+
+
+def test_k_equals_corpus_size_and_max_k(dev):
+    c = datagen.small_corpus(n=1500, d=6000, seed=25)
+    w, S = sketch_both(c, 128, 9, dev)
+    q = [0, 1, 2]
+    gi, gs = gpu_topk(w[q].contiguous(), w[:300].contiguous(), 128, oracle.JS, 300)
+    oi, osc = oracle.topk(sets_rows(S, q), sets_rows(S, np.arange(300)), 128, oracle.JS, 300)
+    assert_topk_equal(gi, gs, oi, osc)
+    gi, gs = gpu_topk(w[q].contiguous(), w, 128, oracle.COS, 1024)
+    oi, osc = oracle.topk(sets_rows(S, q), S, 128, oracle.COS, 1024)
+    assert_topk_equal(gi, gs, oi, osc)
+
+
+@pytest.mark.parametrize("N", [256, 1024, 4096])
+def test_full_size_query_vs_corpus(N, dev):
+    """1,000 queries against 100,000 corpus rows (d = 100,000, log-normal
+    lengths), top-100 Jaccard: sampled queries against the oracle's full sort."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    corpus = _big("corpus", lambda: datagen.lognormal_corpus(100_000))
+    queries = _big("queries", lambda: datagen.lognormal_corpus(1000, seed=datagen.SEED_QUERIES))
+    pi = datagen.random_map(corpus.d, N, datagen.SEED_PI + N)
+    C, _ = bs.sketch(to_dev(corpus.indptr, dev), to_dev(corpus.indices, dev), to_dev(pi, dev), N)
+    Q, _ = bs.sketch(to_dev(queries.indptr, dev), to_dev(queries.indices, dev), to_dev(pi, dev), N)
+    idx, sc = bs.topk(Q, C, N, "js", 100)
+    torch.cuda.synchronize()
+    SC = oracle.sketch_sets(corpus.indptr, corpus.indices, corpus.d, pi, N)
+    SQ = oracle.sketch_sets(queries.indptr, queries.indices, queries.d, pi, N)
+    sample = np.arange(0, 1000, 125)
+    oi, osc = oracle.topk(sets_rows(SQ, sample), SC, N, oracle.JS, 100)
+    assert_topk_equal(idx.cpu().numpy()[sample], sc.cpu().numpy()[sample], oi, osc)
+    # every query: scores non-increasing, indices distinct and in range
+    s = sc.cpu().numpy()
+    i = idx.cpu().numpy()
+    assert (np.diff(s, axis=1) <= 0).all()
+    assert all(len(set(r)) == 100 for r in i) and i.min() >= 0 and i.max() < 100_000
+
+
+def _big(key, fn):
+    from conftest import shared_input
+    return shared_input({"corpus": "corpus100k", "queries": "queries1k"}[key], fn)
