@@ -1,0 +1,311 @@
+#!/usr/bin/env python3
+"""BinSketch hot-path benchmark on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+  1. sketch the corpus: 100,000 binary vectors, d = 100,000, row lengths
+     round(log-normal) with mean 230 and sd 150, Zipf(1.1) feature popularity;
+  2. sketch the queries: 1,000 vectors from the same generator, another seed;
+  3. score every query against every corpus row by the Jaccard estimator and
+     keep the top 100 per query (FP32 scores).
+at sketch width N = 1024 (also reported: N = 256 and N = 4096).
+
+Inputs are resident in device memory before timing starts. The timed region
+is exactly `--steps` steps between two device synchronisations. Per-kernel
+launch durations come from HIP events that the library records on the
+launching stream while timing is enabled.
+
+Printed: one JSON line (see the keys below). `value` is pair estimates per
+second of the whole step (sketching included).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# int32 VALU: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_digest(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "topk_scan": ["paper_1910_04658_amd/csrc/topk.hip", "paper_1910_04658_amd/csrc/bs_common.h"],
+    "sketch_csr": ["paper_1910_04658_amd/csrc/sketch.hip", "paper_1910_04658_amd/csrc/bs_common.h"],
+}
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/traffic.json),
+    or None when no record exists or the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))[kernel][workload]
+    except (KeyError, ValueError):
+        return None
+    if rec.get("src_sha") != src_digest(KERNEL_SOURCES[kernel]):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def make_inputs(N_list, dev):
+    import torch
+
+    import datagen
+    t = time.time()
+    corpus = datagen.lognormal_corpus(100_000, d=100_000, mean=230.0, sd=150.0, seed=datagen.SEED_CORPUS)
+    queries = datagen.lognormal_corpus(1000, d=100_000, mean=230.0, sd=150.0, seed=datagen.SEED_QUERIES)
+    log("inputs generated in %.1fs: corpus nnz %d (mean %.1f), queries nnz %d" % (
+        time.time() - t, corpus.nnz, corpus.nnz / corpus.n, queries.nnz))
+    pis = {N: datagen.random_map(corpus.d, N, datagen.SEED_PI + N) for N in N_list}
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    dev_in = {"c_indptr": to(corpus.indptr), "c_indices": to(corpus.indices),
+              "q_indptr": to(queries.indptr), "q_indices": to(queries.indices),
+              "pi": {N: to(p) for N, p in pis.items()}}
+    return corpus, queries, pis, dev_in
+
+
+class Step:
+    """Preallocated outputs and workspace for one width N."""
+
+    def __init__(self, dev_in, N, k, nC, nQ, dev):
+        import torch
+
+        from paper_1910_04658_amd import binding as bs
+        self.bs = bs
+        self.N, self.k = N, k
+        W = N // 64
+        self.d = dev_in
+        self.pi = dev_in["pi"][N]
+        self.C = torch.empty((nC, W), dtype=torch.int64, device=dev)
+        self.Q = torch.empty((nQ, W), dtype=torch.int64, device=dev)
+        self.popC = torch.empty(nC, dtype=torch.int32, device=dev)
+        self.popQ = torch.empty(nQ, dtype=torch.int32, device=dev)
+        self.idx = torch.empty((nQ, k), dtype=torch.int32, device=dev)
+        self.score = torch.empty((nQ, k), dtype=torch.float32, device=dev)
+        self.ws = bs._workspace(bs.topk_workspace_size(nQ, nC, N, k), dev)
+
+    def __call__(self):
+        bs, d = self.bs, self.d
+        bs.sketch(d["c_indptr"], d["c_indices"], self.pi, self.N, out=self.C, popcounts=self.popC)
+        bs.sketch(d["q_indptr"], d["q_indices"], self.pi, self.N, out=self.Q, popcounts=self.popQ)
+        bs.topk(self.Q, self.C, self.N, "js", self.k, workspace=self.ws, out_idx=self.idx,
+                out_score=self.score)
+
+
+def timed(step, steps, warmup):
+    import torch
+    bs = step.bs
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    bs.timing_collect()
+    bs.timing_reset()
+    bs.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    bs.timing_enable(False)
+    bad = bs.timing_collect()
+    kt = {}
+    for name in ["sketch_csr", "topk_prep", "topk_sample", "topk_scan", "topk_select", "topk_fallback"]:
+        ms, n = bs.timing_get(name)
+        if n:
+            kt[name] = {"avg_ms": ms / n, "launches": n}
+    if bad:
+        log("warning: %d kernel timing events could not be read" % bad)
+    return (t1 - t0) * 1e3 / steps, kt
+
+
+def jaccard_mse(step, corpus, queries):
+    """Closed-form Jaccard estimates vs exact Jaccard on (a) every pair of the
+    1,000 queries with the first 2,000 corpus rows and (b) the returned top-100
+    pairs. Exact values by sparse products on the host."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    bs = step.bs
+
+    def mat(c, rows=None):
+        m = sp.csr_matrix((np.ones(c.nnz, np.float64), c.indices, c.indptr), shape=(c.n, c.d))
+        return m if rows is None else m[rows]
+
+    Qm = mat(queries)
+    Cm = mat(corpus, np.arange(2000))
+    inter = (Qm @ Cm.T).toarray()
+    la = np.asarray(Qm.sum(1)).ravel()[:, None]
+    lb = np.asarray(Cm.sum(1)).ravel()[None, :]
+    exact = inter / (la + lb - inter)
+    est = bs.estimate(step.Q, step.C[:2000].contiguous(), step.N, measures=("js",))["js"]
+    torch.cuda.synchronize()
+    mse_random = float(np.mean((est.cpu().numpy() - exact) ** 2))
+    idx = step.idx.cpu().numpy()
+    sc = step.score.cpu().numpy().astype(np.float64)
+    Cfull = mat(corpus)
+    errs = []
+    for q in range(0, idx.shape[0], 10):
+        sub = Cfull[idx[q]]
+        it = np.asarray((Qm[q] @ sub.T).todense()).ravel()
+        lbq = np.asarray(sub.sum(1)).ravel()
+        ex = it / (la[q, 0] + lbq - it)
+        errs.append((sc[q] - ex) ** 2)
+    mse_top = float(np.mean(np.concatenate(errs)))
+    mean_js_top = float(np.mean(sc[::10]))
+    return {"random_pairs": mse_random, "random_pairs_n": int(exact.size),
+            "top100_pairs": mse_top, "top100_mean_estimate": mean_js_top}
+
+
+def cpu_baseline(corpus, queries, pi, N, k, nq):
+    """The CPU oracle (plain C, OpenMP over rows) on a bounded sample."""
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
+    used = oracle.set_threads(threads)
+    t = time.perf_counter()
+    S = oracle.sketch_sets(corpus.indptr, corpus.indices, corpus.d, pi, N)
+    oracle.pack(S, N)
+    t_sk = time.perf_counter() - t
+    SQ = oracle.sketch_sets(queries.indptr, queries.indices, queries.d, pi, N)
+    sub = oracle.Sets(SQ.vals, SQ.start[:nq], SQ.length[:nq])
+    t = time.perf_counter()
+    oracle.topk(sub, S, N, oracle.JS, k)
+    t_tk = time.perf_counter() - t
+    pairs = nq * corpus.n
+    return {"value": pairs / t_tk, "unit": "pair estimates/s", "cores": used, "kind": "oracle",
+            "sample": "oracle top-%d Jaccard of %d queries x %d corpus rows at N=%d (%.1f s); "
+                      "oracle sketch of all %d corpus rows (%.2f s)" % (
+                          k, nq, corpus.n, N, t_tk, corpus.n, t_sk),
+            "sketch_vectors_per_s": corpus.n / t_sk}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--N", type=int, default=1024)
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--other-widths", default="256,4096", help="extra widths reported (empty: none)")
+    ap.add_argument("--cpu-queries", type=int, default=256, help="queries in the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mse", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(requested --gpus %d, WORLD_SIZE %d)." % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    others = [int(x) for x in args.other_widths.split(",") if x.strip()]
+    widths = [args.N] + [n for n in others if n != args.N]
+    corpus, queries, pis, dev_in = make_inputs(widths, dev)
+    nC, nQ, k = corpus.n, queries.n, args.k
+
+    results = {}
+    for i, N in enumerate(widths):
+        step = Step(dev_in, N, k, nC, nQ, dev)
+        steps = args.steps if i == 0 else max(10, args.steps // 4)
+        ms, kt = timed(step, steps, args.warmup)
+        results[N] = (step, ms, kt, steps)
+        log("N=%d: %.4f ms/step; kernels %s" % (N, ms, {n: round(v["avg_ms"], 4) for n, v in kt.items()}))
+
+    step, ms, kt, steps = results[args.N]
+    pairs = nQ * nC
+    value = pairs / (ms / 1e3)
+
+    def scan_roofline(N, kt):
+        S = min(nC, 4096)
+        if "topk_scan" not in kt:
+            return None
+        ops = nQ * (nC - S) * (N // 16)  # one AND and one popcount per 32-bit word pair
+        t = kt["topk_scan"]["avg_ms"] / 1e3
+        ach = ops / t / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                "frac": ach / PEAK_VALU_TOPS, "traffic": traffic_for("topk_scan", "N%d" % N),
+                "kernel": "topk_scan", "ops_per_launch": ops, "avg_launch_ms": kt["topk_scan"]["avg_ms"]}
+
+    def sketch_roofline(N, kt):
+        if "sketch_csr" not in kt:
+            return None
+        # per launch: the corpus launch and the query launch alternate; use the byte-weighted mean
+        rows = nC + nQ
+        nnz = corpus.nnz + queries.nnz
+        by = (rows + 2) * 4 + nnz * 4 + rows * (N // 8) + rows * 4 + 2 * corpus.d * 4
+        t = kt["sketch_csr"]["avg_ms"] * 2 / 1e3  # two launches per step
+        ach = by / t / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach / PEAK_HBM_GBS,
+                "traffic": traffic_for("sketch_csr", "N%d" % N), "kernel": "sketch_csr",
+                "bytes_per_step": by, "avg_launch_ms": kt["sketch_csr"]["avg_ms"]}
+
+    out = {
+        "metric": "sketched vectors/s + pair estimates/s at N=1024; Jaccard MSE vs exact",
+        "value": value,
+        "unit": "pair estimates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "BinSketch sketch + top-100 Jaccard query-vs-corpus", "N": args.N,
+                   "n_corpus": nC, "n_queries": nQ, "d": corpus.d, "k": k,
+                   "row_length": "round(lognormal), mean 230, sd 150",
+                   "feature_popularity": "Zipf(1.1)", "score_dtype": "f32", "parallelism": "single GPU"},
+        "sketched_vectors_per_s": (nC + nQ) / (kt["sketch_csr"]["avg_ms"] * 2 / 1e3) if "sketch_csr" in kt else None,
+        "pair_estimates_per_s": value,
+        "kernels_ms": {n: v["avg_ms"] for n, v in kt.items()},
+        "roofline": scan_roofline(args.N, kt),
+        "roofline_sketch": sketch_roofline(args.N, kt),
+    }
+    out["widths"] = {}
+    for N in widths:
+        if N == args.N:
+            continue
+        st, msN, ktN, stepsN = results[N]
+        out["widths"][str(N)] = {"ms_per_step": msN, "pair_estimates_per_s": pairs / (msN / 1e3),
+                                 "sketched_vectors_per_s": (nC + nQ) / (ktN["sketch_csr"]["avg_ms"] * 2 / 1e3),
+                                 "kernels_ms": {n: v["avg_ms"] for n, v in ktN.items()},
+                                 "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
+    if not args.no_mse:
+        out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample ...")
+        out["cpu_baseline"] = cpu_baseline(corpus, queries, pis[args.N], args.N, k, args.cpu_queries)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -152,6 +152,22 @@ bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, int64_t nC, 
                   void* workspace, size_t workspace_bytes, void* stream);
 
 /*
+ * Kernel timing for benchmarks and profiling (off by default). While enabled,
+ * every launch is bracketed by two HIP events recorded on the caller's
+ * stream (so it must not be used under graph capture). bs_timing_collect
+ * waits for the recorded events and adds each kernel's elapsed time to a
+ * per-name total ("sketch_csr", "pair_and_popcount", "pair_estimate",
+ * "topk_prep", "topk_sample", "topk_scan", "topk_select", "topk_fallback");
+ * it returns the number of event pairs that could not be read.
+ * bs_timing_get returns 1 and the total milliseconds and launch count for a
+ * name, or 0 if the name has not been timed. Process-wide, thread-safe.
+ */
+int bs_timing_enable(int on);
+int bs_timing_collect(void);
+void bs_timing_reset(void);
+int bs_timing_get(const char* name, double* total_ms, int64_t* count);
+
+/*
  * Testing hook, not for production callers: caps the per-query candidate
  * list of bs_topk at `cap` entries (0 restores the automatic size) so that
  * tests can drive the overflow path, which must return the same result.

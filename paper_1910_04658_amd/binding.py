@@ -62,6 +62,13 @@ def load():
             L.bs_topk_workspace_size.restype = sz
             L.bs_topk.argtypes = [p, i64, p, i64, i32, i32, i32, p, p, p, sz, p]
             L.bs_topk.restype = ctypes.c_int
+            L.bs_timing_enable.argtypes = [ctypes.c_int]
+            L.bs_timing_enable.restype = ctypes.c_int
+            L.bs_timing_collect.restype = ctypes.c_int
+            L.bs_timing_reset.restype = None
+            L.bs_timing_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]
+            L.bs_timing_get.restype = ctypes.c_int
             L.bs_debug_set_topk_capacity.argtypes = [i64]
             L.bs_debug_set_topk_capacity.restype = ctypes.c_int
             _lib = L
@@ -218,3 +225,23 @@ def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool
 
 def debug_set_topk_capacity(cap: int):
     load().bs_debug_set_topk_capacity(int(cap))
+
+
+def timing_enable(on: bool = True):
+    load().bs_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    load().bs_timing_reset()
+
+
+def timing_collect() -> int:
+    return int(load().bs_timing_collect())
+
+
+def timing_get(name: str):
+    """(total milliseconds, launch count) recorded for a kernel name."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    load().bs_timing_get(name.encode(), ctypes.byref(ms), ctypes.byref(n))
+    return ms.value, n.value

@@ -24,6 +24,20 @@ inline bs_status launch_status() {
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Records a pair of HIP events around the launches in its scope when timing
+// is enabled (bs_timing_enable); otherwise does nothing.
+class ScopedTiming {
+ public:
+  ScopedTiming(const char* name, hipStream_t s);
+  ~ScopedTiming();
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t start_ = nullptr;
+  hipEvent_t stop_ = nullptr;
+};
+
 // ---- device helpers -------------------------------------------------------
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -3,11 +3,53 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <string>
+#include <vector>
 
 #include "bs_common.h"
 
 namespace bs {
+
+// ---- opt-in kernel timing with HIP events ------------------------------------
+namespace {
+struct Pending {
+  std::string name;
+  hipEvent_t start, stop;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<Pending> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, std::pair<double, int64_t>> g_totals;
+
+hipEvent_t take_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+ScopedTiming::ScopedTiming(const char* name, hipStream_t s) : name_(name), s_(s) {
+  std::lock_guard<std::mutex> lock(g_tmu);
+  if (!g_timing) return;
+  start_ = take_event();
+  stop_ = take_event();
+  if (start_ && stop_) hipEventRecord(start_, s_);
+}
+
+ScopedTiming::~ScopedTiming() {
+  std::lock_guard<std::mutex> lock(g_tmu);
+  if (!start_ || !stop_) return;
+  hipEventRecord(stop_, s_);
+  g_pending.push_back(Pending{name_, start_, stop_});
+}
 
 bs_status check_device() {
   static std::mutex mu;
@@ -48,3 +90,46 @@ extern "C" const char* bs_status_string(int status) {
 }
 
 extern "C" int32_t bs_words(int32_t N) { return bs::valid_width(N) ? N / 64 : 0; }
+
+extern "C" int bs_timing_enable(int on) {
+  std::lock_guard<std::mutex> lock(bs::g_tmu);
+  bs::g_timing = on != 0;
+  return 0;
+}
+
+extern "C" int bs_timing_collect(void) {
+  std::lock_guard<std::mutex> lock(bs::g_tmu);
+  int bad = 0;
+  for (auto& p : bs::g_pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(p.stop) == hipSuccess && hipEventElapsedTime(&ms, p.start, p.stop) == hipSuccess) {
+      auto& t = bs::g_totals[p.name];
+      t.first += ms;
+      t.second += 1;
+    } else {
+      ++bad;
+    }
+    bs::g_pool.push_back(p.start);
+    bs::g_pool.push_back(p.stop);
+  }
+  bs::g_pending.clear();
+  return bad;
+}
+
+extern "C" void bs_timing_reset(void) {
+  std::lock_guard<std::mutex> lock(bs::g_tmu);
+  bs::g_totals.clear();
+}
+
+extern "C" int bs_timing_get(const char* name, double* total_ms, int64_t* count) {
+  std::lock_guard<std::mutex> lock(bs::g_tmu);
+  auto it = bs::g_totals.find(name ? name : "");
+  if (it == bs::g_totals.end()) {
+    if (total_ms) *total_ms = 0.0;
+    if (count) *count = 0;
+    return 0;
+  }
+  if (total_ms) *total_ms = it->second.first;
+  if (count) *count = it->second.second;
+  return 1;
+}

@@ -167,6 +167,7 @@ bs_status launch_dense(DenseArgs a, hipStream_t s) {
   if (bblocks > INT32_MAX || ablocks > 65535) return BS_ERR_ARG;
   dim3 grid((unsigned)bblocks, (unsigned)ablocks);
   dim3 block(kPairThreads);
+  ScopedTiming timing(EST ? "pair_estimate" : "pair_and_popcount", s);
 #define BS_DENSE_CASE(wc, ta)                                                          \
   case wc:                                                                             \
     hipLaunchKernelGGL((pair_dense_kernel<wc, ta, EST>), grid, block, 0, s, a); \

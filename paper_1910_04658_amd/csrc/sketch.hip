@@ -175,6 +175,7 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
   const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > INT32_MAX) return BS_ERR_ARG;
   const size_t lds_bytes = (size_t)kWavesPerBlock * a.stride * sizeof(uint32_t);
+  ScopedTiming timing("sketch_csr", as_stream(stream));
   hipLaunchKernelGGL(sketch_csr_kernel, dim3((unsigned)blocks), dim3(kWavesPerBlock * kWave),
                      lds_bytes, as_stream(stream), a);
   return launch_status();

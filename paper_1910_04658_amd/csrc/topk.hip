@@ -488,6 +488,7 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
   // 1. sample
   {
     const size_t lds = (size_t)W64 * 8 + (size_t)p.S * 8;
+    ScopedTiming timing("topk_sample", s);
     hipLaunchKernelGGL((topk_sample_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
   }
   // 2. scan the rest of the corpus
@@ -505,6 +506,7 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
     const size_t lds = (size_t)((a.N + 1 + 3) & ~3) * 4 + (size_t)(kThreads / kWave) * kStage * sizeof(Staged);
     int WC = 64;
     while (a.W32 % WC) WC >>= 1;
+    ScopedTiming timing("topk_scan", s);
 #define BS_SCAN_CASE(wc)                                                                          \
   case wc:                                                                                        \
     hipLaunchKernelGGL((topk_scan_kernel<wc, M>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
@@ -525,11 +527,13 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
   // 3. select
   {
     const size_t lds = (size_t)a.kpad * 8 + (size_t)kSelectLdsKeys * 8;
+    ScopedTiming timing("topk_select", s);
     hipLaunchKernelGGL((topk_select_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
   }
   // 4. fallback for overflowed queries (exits at once when none overflowed)
   if (p.S < a.nC) {
     const size_t lds = (size_t)a.kpad * 8 + (size_t)W64 * 8;
+    ScopedTiming timing("topk_fallback", s);
     hipLaunchKernelGGL((topk_fallback_kernel<M>), dim3((unsigned)p.F), dim3(kThreads), lds, s, a);
   }
   return launch_status();
@@ -594,9 +598,12 @@ extern "C" bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, i
   while (kpad < k) kpad <<= 1;
   a.kpad = kpad;
   hipStream_t s = as_stream(stream);
-  launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
-  launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
-  launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
+  {
+    ScopedTiming timing("topk_prep", s);
+    launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
+    launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
+    launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
+  }
   st = launch_status();
   if (st != BS_OK) return st;
   switch (measure) {
