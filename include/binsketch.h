@@ -123,14 +123,18 @@ bs_status bs_and_popcount(const uint64_t* A, int64_t nA, const uint64_t* B, int6
  * which equals Algorithm 1 exactly whenever no count reaches N, with
  * Hamming read as |a| + |b| - 2 IP (the number of differing coordinates).
  * Negative estimates are returned unclamped.
+ *   popA, popB int32[nA], int32[nB]: the row popcounts |a_s| (Algorithm 1,
+ *              first step) exactly as bs_sketch writes them, or NULL to have
+ *              them computed here. Wrong values give wrong estimates.
  *   workspace  device buffer of at least bs_estimate_workspace_size(nA, nB, N)
  *              bytes, 256-byte aligned; overwritten (the T table and the row
  *              popcounts |a_s|, |b_s| of Algorithm 1, first step).
  */
 size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N);
-bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB, int32_t N,
-                      double* ip, double* ham, double* js, double* cos, void* workspace,
-                      size_t workspace_bytes, void* stream);
+bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                      const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
+                      double* js, double* cos, void* workspace, size_t workspace_bytes,
+                      void* stream);
 
 /*
  * bs_topk — for every query row Q_p, the k corpus rows C_q with the best
@@ -139,6 +143,7 @@ bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t 
  * BS_COSINE, lowest first for BS_HAMMING; ties go to the smaller corpus index.
  *
  *   Q          uint64[nQ][N/64] query sketches;  C uint64[nC][N/64] corpus.
+ *   popQ, popC row popcounts as bs_sketch writes them, or NULL (computed here).
  *   k          1 <= k <= min(nC, BS_MAX_K).
  *   out_idx    int32[nQ][k]   corpus row indices, best first.
  *   out_score  float[nQ][k]   their scores, or NULL to skip.
@@ -147,9 +152,10 @@ bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t 
  * The result does not depend on the launch configuration or on timing.
  */
 size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int32_t k);
-bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, int64_t nC, int32_t N,
-                  int32_t measure, int32_t k, int32_t* out_idx, float* out_score,
-                  void* workspace, size_t workspace_bytes, void* stream);
+bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint64_t* C,
+                  const int32_t* popC, int64_t nC, int32_t N, int32_t measure, int32_t k,
+                  int32_t* out_idx, float* out_score, void* workspace, size_t workspace_bytes,
+                  void* stream);
 
 /*
  * Kernel timing for benchmarks and profiling (off by default). While enabled,

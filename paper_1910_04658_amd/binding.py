@@ -56,11 +56,11 @@ def load():
             L.bs_and_popcount.restype = ctypes.c_int
             L.bs_estimate_workspace_size.argtypes = [i64, i64, i32]
             L.bs_estimate_workspace_size.restype = sz
-            L.bs_estimate.argtypes = [p, i64, p, i64, i32, p, p, p, p, p, sz, p]
+            L.bs_estimate.argtypes = [p, p, i64, p, p, i64, i32, p, p, p, p, p, sz, p]
             L.bs_estimate.restype = ctypes.c_int
             L.bs_topk_workspace_size.argtypes = [i64, i64, i32, i32]
             L.bs_topk_workspace_size.restype = sz
-            L.bs_topk.argtypes = [p, i64, p, i64, i32, i32, i32, p, p, p, sz, p]
+            L.bs_topk.argtypes = [p, p, i64, p, p, i64, i32, i32, i32, p, p, p, sz, p]
             L.bs_topk.restype = ctypes.c_int
             L.bs_timing_enable.argtypes = [ctypes.c_int]
             L.bs_timing_enable.restype = ctypes.c_int
@@ -167,12 +167,24 @@ def and_popcount(A: torch.Tensor, B: torch.Tensor, N: int, out: torch.Tensor | N
     return out
 
 
+def _opt_pop(t, n, name):
+    if t is None:
+        return None
+    _need(t, name, torch.int32, 1)
+    if t.numel() != n:
+        raise ValueError("%s must have one entry per row" % name)
+    return t
+
+
 def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "js", "cos"),
-             workspace: torch.Tensor | None = None):
+             workspace: torch.Tensor | None = None, popA: torch.Tensor | None = None,
+             popB: torch.Tensor | None = None):
     """bs_estimate: dict measure -> float64[nA][nB]."""
     W = words(N)
     _need(A, "A", torch.int64, 2)
     _need(B, "B", torch.int64, 2)
+    popA = _opt_pop(popA, A.shape[0], "popA")
+    popB = _opt_pop(popB, B.shape[0], "popB")
     if A.shape[1] != W or B.shape[1] != W:
         raise ValueError("sketch rows must hold N/64 words")
     nA, nB = A.shape[0], B.shape[0]
@@ -185,7 +197,8 @@ def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "j
     need = L.bs_estimate_workspace_size(nA, nB, int(N))
     if workspace is None:
         workspace = _workspace(need, A.device)
-    st = L.bs_estimate(_ptr(A), nA, _ptr(B), nB, int(N), _ptr(outs.get("ip")), _ptr(outs.get("ham")),
+    st = L.bs_estimate(_ptr(A), _ptr(popA), nA, _ptr(B), _ptr(popB), nB, int(N), _ptr(outs.get("ip")),
+                       _ptr(outs.get("ham")),
                        _ptr(outs.get("js")), _ptr(outs.get("cos")), _ptr(workspace), workspace.numel(),
                        _stream())
     _check(st, "bs_estimate")
@@ -198,12 +211,15 @@ def topk_workspace_size(nQ: int, nC: int, N: int, k: int) -> int:
 
 def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool = True,
          workspace: torch.Tensor | None = None, out_idx: torch.Tensor | None = None,
-         out_score: torch.Tensor | None = None):
+         out_score: torch.Tensor | None = None, popQ: torch.Tensor | None = None,
+         popC: torch.Tensor | None = None):
     """bs_topk: (idx int32[nQ][k], score float32[nQ][k] or None)."""
     m = MEASURES[measure] if isinstance(measure, str) else int(measure)
     W = words(N)
     _need(Q, "Q", torch.int64, 2)
     _need(C, "C", torch.int64, 2)
+    popQ = _opt_pop(popQ, Q.shape[0], "popQ")
+    popC = _opt_pop(popC, C.shape[0], "popC")
     if Q.shape[1] != W or C.shape[1] != W:
         raise ValueError("sketch rows must hold N/64 words")
     nQ, nC = Q.shape[0], C.shape[0]
@@ -217,7 +233,8 @@ def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool
         raise ValueError("invalid top-k arguments (nC=%d, N=%d, k=%d)" % (nC, N, k))
     if workspace is None:
         workspace = _workspace(need, Q.device)
-    st = L.bs_topk(_ptr(Q), nQ, _ptr(C), nC, int(N), m, int(k), _ptr(out_idx), _ptr(out_score),
+    st = L.bs_topk(_ptr(Q), _ptr(popQ), nQ, _ptr(C), _ptr(popC), nC, int(N), m, int(k), _ptr(out_idx),
+                   _ptr(out_score),
                    _ptr(workspace), workspace.numel(), _stream())
     _check(st, "bs_topk")
     return out_idx, out_score

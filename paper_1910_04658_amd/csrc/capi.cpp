@@ -41,13 +41,13 @@ ScopedTiming::ScopedTiming(const char* name, hipStream_t s) : name_(name), s_(s)
   if (!g_timing) return;
   start_ = take_event();
   stop_ = take_event();
-  if (start_ && stop_) hipEventRecord(start_, s_);
+  if (start_ && stop_) (void)hipEventRecord(start_, s_);
 }
 
 ScopedTiming::~ScopedTiming() {
   std::lock_guard<std::mutex> lock(g_tmu);
   if (!start_ || !stop_) return;
-  hipEventRecord(stop_, s_);
+  (void)hipEventRecord(stop_, s_);
   g_pending.push_back(Pending{name_, start_, stop_});
 }
 

@@ -215,9 +215,10 @@ extern "C" size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N) 
          align256((size_t)nB * 4);
 }
 
-extern "C" bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB,
-                                 int32_t N, double* ip, double* ham, double* js, double* cos,
-                                 void* workspace, size_t workspace_bytes, void* stream) {
+extern "C" bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                                 const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
+                                 double* js, double* cos, void* workspace, size_t workspace_bytes,
+                                 void* stream) {
   using namespace bs;
   if (nA < 0 || nB < 0 || !valid_width(N)) return BS_ERR_ARG;
   if ((!A && nA > 0) || (!B && nB > 0)) return BS_ERR_NULL;
@@ -232,20 +233,20 @@ extern "C" bs_status bs_estimate(const uint64_t* A, int64_t nA, const uint64_t* 
   char* ws = static_cast<char*>(workspace);
   double* t64 = reinterpret_cast<double*>(ws);
   ws += align256((size_t)(N + 1) * sizeof(double));
-  int32_t* popA = reinterpret_cast<int32_t*>(ws);
+  int32_t* wpopA = reinterpret_cast<int32_t*>(ws);
   ws += align256((size_t)nA * 4);
-  int32_t* popB = reinterpret_cast<int32_t*>(ws);
+  int32_t* wpopB = reinterpret_cast<int32_t*>(ws);
   hipStream_t s = as_stream(stream);
   launch_lut(N, t64, nullptr, s);
-  launch_row_popcount(A, nA, N, popA, s);
-  launch_row_popcount(B, nB, N, popB, s);
+  if (!popA) launch_row_popcount(A, nA, N, wpopA, s);
+  if (!popB) launch_row_popcount(B, nB, N, wpopB, s);
   st = launch_status();
   if (st != BS_OK) return st;
   DenseArgs a = {};
   a.A = reinterpret_cast<const uint32_t*>(A);
   a.B = reinterpret_cast<const uint32_t*>(B);
-  a.popA = popA;
-  a.popB = popB;
+  a.popA = popA ? popA : wpopA;
+  a.popB = popB ? popB : wpopB;
   a.t64 = t64;
   a.ip = ip;
   a.ham = ham;

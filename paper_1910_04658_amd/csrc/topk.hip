@@ -41,6 +41,9 @@ constexpr int kSampleMax = 4096;     // rows scored in the sample pass
 constexpr int kSelectLdsKeys = 4096; // candidate keys selected in LDS (else in place)
 constexpr int kStage = 128;          // per-wave staging entries in the scan pass
 constexpr int kFallbackBlocks = 16;
+// Candidate counters sit one per 256-byte line: every corpus slab bumps every
+// query's counter, and atomics that share a line serialise.
+constexpr int kCntStride = 64;
 
 struct QConst {  // per-query constants written by the sample pass
   float tau;     // k-th best sample score
@@ -52,7 +55,8 @@ struct QConst {  // per-query constants written by the sample pass
 
 struct Plan {
   int64_t S, stride, cap, F;
-  size_t off_t32, off_popq, off_popc, off_qc, off_cnt, off_cand, off_scratch, total;
+  size_t off_t32, off_popq, off_popc, off_qc, off_cnt, off_cand, off_scratch, off_mtab, off_ovf, off_skeys,
+      off_sxab, total;
 };
 
 Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
@@ -80,11 +84,19 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   p.off_qc = o;
   o += align256((size_t)nQ * sizeof(QConst));
   p.off_cnt = o;
-  o += align256((size_t)nQ * 4);
+  o += align256((size_t)nQ * 4 * kCntStride);
   p.off_cand = o;
   o += align256((size_t)nQ * (size_t)p.cap * 8);
   p.off_scratch = o;
   o += align256((size_t)p.F * (size_t)nC * 8);
+  p.off_mtab = o;
+  o += align256((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
+  p.off_ovf = o;
+  o += align256((size_t)(nQ + 1) * 4);
+  p.off_skeys = o;
+  o += align256((size_t)nQ * (size_t)p.S * 4);
+  p.off_sxab = o;
+  o += align256((size_t)nQ * (size_t)p.S * 4);
   p.total = o;
   return p;
 }
@@ -132,13 +144,21 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) 
   return v + add;
 }
 
-// The k-th largest of n keys (1 <= k <= n), by MSB-first radix select over
-// 8-bit digits. `keys` may point to LDS or global memory. Block-wide call.
+// MSB-first radix select over 8-bit digits of the k largest of n keys
+// (1 <= k <= n). On return the k largest are exactly the keys with
+// (key & *pmask_out) >= prefix (the return value): either all digits were
+// resolved (then prefix is the k-th largest key itself) or, with `early`, the
+// digit bin holding the k-th key held exactly the keys still needed, so the
+// remaining digits need not be looked at. `keys` may point to LDS or global
+// memory. Block-wide call.
 template <typename K>
 __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, uint32_t* wsum,
-                              K* bcast_prefix, int64_t* bcast_need) {
+                              K* bcast_prefix, int64_t* bcast_need, K* pmask_out = nullptr,
+                              bool early = false) {
+  __shared__ int done;
   K prefix = 0, pmask = 0;
   int64_t need = k;
+  if (threadIdx.x == 0) done = 0;
   for (int shift = (int)sizeof(K) * 8 - 8; shift >= 0; shift -= 8) {
     hist[threadIdx.x] = 0;
     __syncthreads();
@@ -155,13 +175,17 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
     if ((int64_t)excl < need && (int64_t)incl >= need) {
       *bcast_prefix = prefix | ((K)b << shift);
       *bcast_need = need - (int64_t)excl;
+      if (early && (int64_t)incl == need) done = 1;
     }
     __syncthreads();
     prefix = *bcast_prefix;
     need = *bcast_need;
     pmask |= ((K)255) << shift;
+    const int stop = done;
     __syncthreads();
+    if (stop) break;
   }
+  if (pmask_out) *pmask_out = pmask;
   return prefix;
 }
 
@@ -191,12 +215,16 @@ struct TopkArgs {
   const int32_t* __restrict__ popQ;
   const int32_t* __restrict__ popC;
   QConst* __restrict__ qc;
-  int32_t* __restrict__ cnt;       // [nQ]
+  int32_t* __restrict__ cnt;       // [nQ][kCntStride], entry 0 used
   uint64_t* __restrict__ cand;     // [nQ][cap]
   uint64_t* __restrict__ scratch;  // [F][nC]
+  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
+  int32_t* __restrict__ ovf;       // [1 + nQ]: count, then the overflowed queries
+  uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
+  int32_t* __restrict__ sxab;      // [nQ][S] sample pair counts
   int32_t* __restrict__ out_idx;   // [nQ][k]
   float* __restrict__ out_score;   // [nQ][k] or null
-  int64_t nQ, nC, S, stride, cap;
+  int64_t nQ, nQp, nC, S, stride, cap;
   int32_t N, W32, k, kpad;
 };
 
@@ -249,50 +277,134 @@ __device__ QConst make_qconst(float tau, float Tq, int32_t xq) {
 }
 
 // ---- pass 1: sample ---------------------------------------------------------
+// 1a. Exact keys of every (query, sample row) pair: lanes hold 64 consecutive
+// sample rows (every stride-th corpus row, words in VGPRs), queries arrive on
+// the scalar unit, and the keys of one query land in 64 consecutive slots.
+// W32T: words per row when it is a compile-time constant, else 0 (generic).
+template <int M, int W32T, bool LDS_LUT>
+__global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a, int64_t qb_size) {
+  extern __shared__ float lut_s[];
+  const float* lut = a.t32;
+  if (LDS_LUT) {
+    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    __syncthreads();
+    lut = lut_s;
+  }
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // sample index
+  const int64_t q_begin = (int64_t)blockIdx.y * qb_size;
+  const int64_t q_end = q_begin + qb_size < a.nQ ? q_begin + qb_size : a.nQ;
+  const bool i_ok = i < a.S;
+  const int64_t row = (i_ok ? i : a.S - 1) * a.stride;
+  const int W32 = W32T ? W32T : a.W32;
+  const uint32_t* crow = reinterpret_cast<const uint32_t*>(a.C) + (size_t)row * W32;
+  const int32_t xc = a.popC[row];
+  const float Tc = lut[xc];
+  constexpr int R = W32T ? W32T : 2;
+  uint32_t cw[R];
+  if (W32T) {
+#pragma unroll
+    for (int w = 0; w < R; ++w) cw[w] = crow[w];
+  }
+  for (int64_t q = q_begin; q < q_end; ++q) {
+    const cptr<uint32_t> qrow = as_const(reinterpret_cast<const uint32_t*>(a.Q) + (size_t)q * W32);
+    uint32_t acc = 0;
+    if (W32T) {
+#pragma unroll
+      for (int w = 0; w < R; ++w) acc += popc32(qrow[w] & cw[w]);
+    } else {
+      for (int w = 0; w < W32; w += 2) {
+        const uint2 c2 = *reinterpret_cast<const uint2*>(crow + w);
+        acc += popc32(qrow[w] & c2.x) + popc32(qrow[w + 1] & c2.y);
+      }
+    }
+    const int32_t xq = as_const(a.popQ)[q];
+    const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc]);
+    if (i_ok) {
+      a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
+      a.sxab[(size_t)q * a.S + i] = (int32_t)acc;
+    }
+  }
+}
+
+// 1b. Per query: the k-th best sample key (LDS radix select), the sample rows
+// scoring at least that, and the per-query constants of the scan filter.
 template <int M>
-__global__ __launch_bounds__(kThreads) void topk_sample_kernel(TopkArgs a) {
-  extern __shared__ uint64_t smem64[];
-  const int W64 = a.W32 / 2;
-  uint64_t* qw = smem64;                                   // [W64]
-  uint32_t* keys = reinterpret_cast<uint32_t*>(qw + W64);  // [S]
-  int32_t* xabs = reinterpret_cast<int32_t*>(keys + a.S);  // [S]
+__global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(TopkArgs a) {
+  extern __shared__ uint32_t keys[];  // [S]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint32_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
   const int64_t q = blockIdx.x;
-  const uint64_t* qrow = a.Q + (size_t)q * W64;
-  for (int w = threadIdx.x; w < W64; w += kThreads) qw[w] = qrow[w];
+  const uint32_t* src = a.skeys + (size_t)q * a.S;
+  for (int64_t i = threadIdx.x; i < a.S; i += kThreads) keys[i] = src[i];
   if (threadIdx.x == 0) nsel = 0;
-  const int32_t xq = a.popQ[q];
-  const float Tq = a.t32[xq];
-  __syncthreads();
-  for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
-    const int64_t row = i * a.stride;
-    const int32_t xab = and_popcount_row(qw, a.C + (size_t)row * W64, W64);
-    const int32_t xc = a.popC[row];
-    const float sc = score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]);
-    keys[i] = score_key<M>(sc);
-    xabs[i] = xab;
-  }
+  if (q == 0 && threadIdx.x == 0) a.ovf[0] = 0;
   __syncthreads();
   const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed);
   uint64_t* cq = a.cand + (size_t)q * a.cap;
+  const int32_t* xab = a.sxab + (size_t)q * a.S;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     if (keys[i] >= tau_key) {
       const uint32_t slot = atomicAdd(&nsel, 1u);
-      cq[slot] = ((uint64_t)(uint32_t)xabs[i] << 32) | (uint32_t)(i * a.stride);
+      cq[slot] = ((uint64_t)(uint32_t)xab[i] << 32) | (uint32_t)(i * a.stride);
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    a.cnt[q] = (int32_t)nsel;
-    a.qc[q] = make_qconst<M>(key_score<M>(tau_key), Tq, xq);
+    const int32_t xq = a.popQ[q];
+    a.cnt[q * kCntStride] = (int32_t)nsel;
+    a.qc[q] = make_qconst<M>(key_score<M>(tau_key), a.t32[xq], xq);
   }
 }
 
-// ---- pass 2: filtered scan ----------------------------------------------------
+// ---- pass 2a: per-query integer thresholds ----------------------------------
+// For query q and a corpus row of weight x_c, every pair scoring >= tau has
+// T(x_u) <= bound(q, x_c) (make_qconst), and since the FP32 table T is
+// non-decreasing that means x_u <= X = max{x : T(x) <= bound}, i.e.
+//   x_ab >= m[x_c][q] = x_q + x_c - X.
+// m is clamped to [0, 65535]: lowering it only admits more candidates.
+constexpr int kBoundX = 64;  // table rows (x_c values) per block of the threshold kernel
+
+template <int M, bool LDS_LUT>
+__global__ __launch_bounds__(kThreads) void topk_bound_kernel(TopkArgs a) {
+  extern __shared__ float lut_s[];
+  const float* lut = a.t32;
+  if (LDS_LUT) {
+    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    __syncthreads();
+    lut = lut_s;
+  }
+  const int64_t qi = (int64_t)blockIdx.x * kWave + threadIdx.x % kWave;
+  if (qi >= a.nQp) return;
+  QConst k = {};
+  const bool q_ok = qi < a.nQ;
+  if (q_ok) k = a.qc[qi];
+  for (int r = threadIdx.x / kWave; r < kBoundX; r += kThreads / kWave) {
+    const int xc = blockIdx.y * kBoundX + r;
+    if (xc > a.N) break;
+    uint16_t m = 65535;
+    if (q_ok) {
+      const float Tc = lut[xc];
+      const float s = k.Tq + Tc;
+      float bound = fmaf(s, k.A, k.C);
+      if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
+      // largest x in [0, N] with T(x) <= bound (T non-decreasing), or -1
+      int lo = -1, hi = a.N;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lut[mid] <= bound) lo = mid;
+        else hi = mid - 1;
+      }
+      const int64_t mm = (int64_t)k.xq + xc - lo;
+      m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
+    }
+    a.mtab[(size_t)xc * a.nQp + qi] = m;
+  }
+}
+
+// ---- pass 2b: filtered scan ----------------------------------------------------
 struct Staged {
   int32_t q, row, xab;
 };
@@ -307,86 +419,172 @@ __device__ __forceinline__ void wave_sync_lds() {
 __device__ __forceinline__ void flush_stage(Staged* st, int n, int lane, const TopkArgs& a) {
   if (lane < n) {
     const Staged e = st[lane];
-    const int32_t slot = atomicAdd(a.cnt + e.q, 1);
+    const int32_t slot = atomicAdd(a.cnt + (size_t)e.q * kCntStride, 1);
     if (slot < a.cap) a.cand[(size_t)e.q * a.cap + slot] = ((uint64_t)(uint32_t)e.xab << 32) | (uint32_t)e.row;
   }
 }
 
-template <int WC, int M>
-__global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t n_ctiles, int64_t nqb,
-                                                             int64_t qb_size) {
-  extern __shared__ float lut[];  // [N+1], then per-wave staging
+// Stage the lanes of `take` (a wave-uniform ballot) and flush full batches.
+__device__ __forceinline__ void stage_take(bool take, int32_t q, int32_t row, int32_t xab, Staged* stage,
+                                           int& fill, int lane, const TopkArgs& a) {
+  const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
+  if (!mask) return;
+  const int pos = fill + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+  if (take) stage[pos] = Staged{q, row, xab};
+  fill += __builtin_popcountll(mask);
+  if (fill >= kWave) {
+    wave_sync_lds();
+    flush_stage(stage, kWave, lane, a);
+    wave_sync_lds();
+    Staged rest = {0, 0, 0};
+    if (lane < fill - kWave) rest = stage[kWave + lane];
+    wave_sync_lds();
+    if (lane < fill - kWave) stage[lane] = rest;
+    fill -= kWave;
+    wave_sync_lds();
+  }
+}
+
+// One wave = QPL groups of 64 queries (one query per lane per group, words in
+// VGPRs) x a slab of corpus rows streamed through the scalar unit in pieces
+// of PS words, each piece fetched one step ahead of its use. The four waves
+// of a block take four query groups of the same slab, so they read the same
+// corpus words (scalar-cache hits after the first). W32T: words per row.
+template <int W32T, int QPL>
+__global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t n_slabs, int64_t slab,
+                                                             int64_t nqb4) {
+  constexpr int PS = W32T < 32 ? W32T : 32;  // words per scalar piece
+  constexpr int P = W32T / PS;               // pieces per row
+  __shared__ Staged stage_all[kThreads / kWave][kStage];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  // XCD-aware tile order: blocks are dealt round-robin to the 8 XCDs, so
-  // give each XCD a contiguous range of (corpus tile, query block) pairs;
-  // the query blocks of one corpus tile then share that XCD's L2.
-  const int64_t nblocks = n_ctiles * nqb;
-  const int64_t per_xcd = (nblocks + 7) / 8;
-  const int64_t bid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (bid >= nblocks) return;
-  const int64_t ct = bid / nqb, qb = bid % nqb;
-  const int64_t q_begin = qb * qb_size;
-  const int64_t q_end = q_begin + qb_size < a.nQ ? q_begin + qb_size : a.nQ;
+  const int64_t bid = blockIdx.x;
+  const int64_t sl = bid / nqb4;
+  const int64_t qg0 = ((bid % nqb4) * (kThreads / kWave) + wid) * QPL;  // first 64-query group
+  Staged* stage = stage_all[wid];
+  const int64_t c_begin = sl * slab;
+  const int64_t c_end = c_begin + slab < a.nC ? c_begin + slab : a.nC;
+  if (qg0 * kWave >= a.nQ || c_begin >= c_end) return;  // wave-uniform
+  const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C);
+  const cptr<int32_t> popC = as_const(a.popC);
 
-  const int Np1 = a.N + 1;
-  for (int x = threadIdx.x; x < Np1; x += kThreads) lut[x] = a.t32[x];
-  Staged* stage = reinterpret_cast<Staged*>(lut + ((Np1 + 3) & ~3)) + (size_t)wid * kStage;
-  __syncthreads();
+  int64_t q[QPL];
+  bool q_ok[QPL];
+  uint32_t qw[QPL][W32T];
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) {
+    q[j] = (qg0 + j) * kWave + lane;
+    q_ok[j] = q[j] < a.nQ;
+    const uint32_t* qrow = reinterpret_cast<const uint32_t*>(a.Q) + (size_t)(q_ok[j] ? q[j] : a.nQ - 1) * W32T;
+#pragma unroll
+    for (int w = 0; w < W32T; ++w) qw[j][w] = qrow[w];
+  }
+  // threshold-table columns; groups past the last one read group qg0 (masked by q_ok)
+  const int64_t ngroups = a.nQp / kWave;
+  int64_t moff[QPL];
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) moff[j] = (qg0 + j < ngroups ? qg0 + j : qg0) * kWave + lane;
+  const uint16_t* mt = a.mtab;
+  int fill = 0;
+  int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row
+  const int64_t s_end = a.S * a.stride;
 
-  const int64_t row = ct * kThreads + threadIdx.x;
-  const bool in_sample = (row % a.stride == 0) && (row / a.stride < a.S);
-  const bool valid = row < a.nC && !in_sample;
-  const int64_t rr = row < a.nC ? row : a.nC - 1;
+  // scalar pipeline state: current piece words, row weights two rows ahead
+  uint32_t cur[PS];
+  {
+    const cptr<uint32_t> r0 = as_const(C32 + (size_t)c_begin * W32T);
+#pragma unroll
+    for (int w = 0; w < PS; ++w) cur[w] = r0[w];
+  }
+  int32_t x1 = popC[c_begin];                                       // weight of row c
+  uint16_t m[QPL];
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) m[j] = mt[(size_t)x1 * a.nQp + moff[j]];
+  int32_t x2 = popC[c_begin + 1 < c_end ? c_begin + 1 : c_begin];  // weight of row c+1
+
+  for (int64_t c = c_begin; c < c_end; ++c) {
+    const int64_t c1 = c + 1 < c_end ? c + 1 : c;
+    const int64_t c2 = c + 2 < c_end ? c + 2 : c1;
+    uint32_t acc[QPL];
+#pragma unroll
+    for (int j = 0; j < QPL; ++j) acc[j] = 0;
+    int32_t x3 = 0;
+    uint16_t mn[QPL];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      // fetch the next piece (the next row's first piece after the last one)
+      uint32_t nxt[PS];
+      const cptr<uint32_t> nr = as_const(C32 + (p + 1 < P ? (size_t)c * W32T + (p + 1) * PS : (size_t)c1 * W32T));
+#pragma unroll
+      for (int w = 0; w < PS; ++w) nxt[w] = nr[w];
+      if (p == 0) {
+        x3 = popC[c2];
+#pragma unroll
+        for (int j = 0; j < QPL; ++j) mn[j] = mt[(size_t)x2 * a.nQp + moff[j]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int j = 0; j < QPL; ++j) {
+#pragma unroll
+        for (int w = 0; w < PS; ++w) acc[j] += popc32(cur[w] & qw[j][p * PS + w]);
+      }
+#pragma unroll
+      for (int w = 0; w < PS; ++w) cur[w] = nxt[w];
+    }
+    const bool in_sample = c == next_s && c < s_end;
+    if (c == next_s) next_s += a.stride;
+#pragma unroll
+    for (int j = 0; j < QPL; ++j) {
+      const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
+      stage_take(take, (int32_t)q[j], (int32_t)c, (int32_t)acc[j], stage, fill, lane, a);
+      m[j] = mn[j];
+    }
+    x2 = x3;
+  }
+  wave_sync_lds();
+  flush_stage(stage, fill, lane, a);
+}
+
+// Generic widths (N not a power of two, or N > 4096): query words re-read per
+// chunk of WC words; correct for every width, tuned for none.
+template <int WC>
+__global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a, int64_t n_slabs, int64_t slab,
+                                                                     int64_t nqb4) {
+  __shared__ Staged stage_all[kThreads / kWave][kStage];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  const int64_t bid = blockIdx.x;
+  const int64_t sl = bid / nqb4;
+  const int64_t qb = (bid % nqb4) * (kThreads / kWave) + wid;
+  const int64_t q = qb * kWave + lane;
+  Staged* stage = stage_all[wid];
+  const int64_t c_begin = sl * slab;
+  const int64_t c_end = c_begin + slab < a.nC ? c_begin + slab : a.nC;
+  if (qb * kWave >= a.nQ || c_begin >= c_end) return;
+  const bool q_ok = q < a.nQ;
   const int W32 = a.W32;
   const int nchunks = W32 / WC;
-  const uint32_t* crow = reinterpret_cast<const uint32_t*>(a.C) + (size_t)rr * W32;
-  const uint32_t* Q32 = reinterpret_cast<const uint32_t*>(a.Q);
-  const int32_t xc = a.popC[rr];
-  const float Tc = lut[xc];
-  const float sqTc = (M == BS_COSINE) ? sqrtf(Tc) : 0.0f;
-
-  uint32_t cw[WC];
-  if (nchunks == 1) {
-#pragma unroll
-    for (int w = 0; w < WC; ++w) cw[w] = crow[w];
-  }
-  int fill = 0;  // wave-uniform count of staged entries
-  for (int64_t q = q_begin; q < q_end; ++q) {
+  const uint32_t* qrow = reinterpret_cast<const uint32_t*>(a.Q) + (size_t)(q_ok ? q : a.nQ - 1) * W32;
+  const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C);
+  const uint16_t* mt = a.mtab + q;
+  int fill = 0;
+  int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;
+  const int64_t s_end = a.S * a.stride;
+  for (int64_t c = c_begin; c < c_end; ++c) {
     uint32_t acc = 0;
-    for (int c = 0; c < nchunks; ++c) {
-      if (nchunks != 1) {
+    for (int ch = 0; ch < nchunks; ++ch) {
+      uint32_t qw[WC];
 #pragma unroll
-        for (int w = 0; w < WC; ++w) cw[w] = crow[c * WC + w];
-      }
-      const cptr<uint32_t> qrow = as_const(Q32 + (size_t)q * W32 + c * WC);
+      for (int w = 0; w < WC; ++w) qw[w] = qrow[ch * WC + w];
+      const cptr<uint32_t> cr = as_const(C32 + (size_t)c * W32 + ch * WC);
 #pragma unroll
-      for (int w = 0; w < WC; ++w) acc += popc32(qrow[w] & cw[w]);
+      for (int w = 0; w < WC; ++w) acc += popc32(cr[w] & qw[w]);
     }
-    const cptr<QConst> k = as_const<QConst>(a.qc) + q;
-    const int32_t xu = k->xq + xc - (int32_t)acc;
-    const float Tu = lut[xu];
-    const float s = k->Tq + Tc;
-    float bound = fmaf(s, k->A, k->C);
-    if (M == BS_COSINE) bound = fmaf(sqTc, k->B, bound);
-    const bool take = valid && Tu <= bound;
-    const uint64_t mask = __ballot(take);
-    if (mask) {
-      const int pos = fill + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-      if (take) stage[pos] = Staged{(int32_t)q, (int32_t)row, (int32_t)acc};
-      fill += __builtin_popcountll(mask);
-      if (fill >= kWave) {
-        wave_sync_lds();
-        flush_stage(stage, kWave, lane, a);
-        wave_sync_lds();
-        Staged rest = {0, 0, 0};
-        if (lane < fill - kWave) rest = stage[kWave + lane];
-        wave_sync_lds();
-        if (lane < fill - kWave) stage[lane] = rest;
-        fill -= kWave;
-        wave_sync_lds();
-      }
-    }
+    const int32_t xc = as_const(a.popC)[c];
+    const uint16_t m = mt[(size_t)xc * a.nQp];
+    const bool in_sample = c == next_s && c < s_end;
+    if (c == next_s) next_s += a.stride;
+    const bool take = q_ok && !in_sample && acc >= (uint32_t)m;
+    stage_take(take, (int32_t)q, (int32_t)c, (int32_t)acc, stage, fill, lane, a);
   }
   wave_sync_lds();
   flush_stage(stage, fill, lane, a);
@@ -402,13 +600,14 @@ template <int M>
 __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a,
                                  uint64_t* sel, uint32_t* hist, uint32_t* wsum, uint64_t* bprefix,
                                  int64_t* bneed, uint32_t* nsel) {
-  const uint64_t kth = radix_select_kth<uint64_t>(keys, n, a.k, hist, wsum, bprefix, bneed);
+  uint64_t pmask = 0;
+  const uint64_t kth = radix_select_kth<uint64_t>(keys, n, a.k, hist, wsum, bprefix, bneed, &pmask, true);
   if (threadIdx.x == 0) *nsel = 0;
   for (int t = threadIdx.x; t < a.kpad; t += kThreads) sel[t] = 0;
   __syncthreads();
   for (int64_t i = threadIdx.x; i < n; i += kThreads) {
     const uint64_t key = keys[i];
-    if (key >= kth) {  // exactly k keys: the keys are unique
+    if ((key & pmask) >= kth) {  // exactly k keys: the keys are unique
       const uint32_t slot = atomicAdd(nsel, 1u);
       if (slot < (uint32_t)a.kpad) sel[slot] = key;
     }
@@ -432,8 +631,11 @@ __global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
   const int64_t q = blockIdx.x;
-  const int64_t n = a.cnt[q];
-  if (n > a.cap) return;  // overflowed: the fallback kernel owns this query
+  const int64_t n = a.cnt[q * kCntStride];
+  if (n > a.cap) {  // overflowed: hand the query to the fallback kernel
+    if (threadIdx.x == 0) a.ovf[1 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    return;
+  }
   uint64_t* sel = sm;
   uint64_t* cq = a.cand + (size_t)q * a.cap;
   uint64_t* keys = n <= kSelectLdsKeys ? sm + a.kpad : cq;
@@ -464,8 +666,9 @@ __global__ __launch_bounds__(kThreads) void topk_fallback_kernel(TopkArgs a) {
   uint64_t* sel = sm;
   uint64_t* qw = sm + a.kpad;
   uint64_t* keys = a.scratch + (size_t)blockIdx.x * a.nC;
-  for (int64_t q = blockIdx.x; q < a.nQ; q += gridDim.x) {
-    if (a.cnt[q] <= a.cap) continue;
+  const int32_t n_ovf = a.ovf[0];
+  for (int32_t i = blockIdx.x; i < n_ovf; i += gridDim.x) {
+    const int64_t q = a.ovf[1 + i];
     const uint64_t* qrow = a.Q + (size_t)q * W64;
     for (int w = threadIdx.x; w < W64; w += kThreads) qw[w] = qrow[w];
     const int32_t xq = a.popQ[q];
@@ -487,42 +690,83 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
   const int W64 = a.W32 / 2;
   // 1. sample
   {
-    const size_t lds = (size_t)W64 * 8 + (size_t)p.S * 8;
     ScopedTiming timing("topk_sample", s);
-    hipLaunchKernelGGL((topk_sample_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
-  }
-  // 2. scan the rest of the corpus
-  if (p.S < a.nC) {
-    const int64_t n_ctiles = (a.nC + kThreads - 1) / kThreads;
-    // query blocks: enough (tile, block) pairs for ~16 blocks per CU
-    int64_t nqb = (4096 + n_ctiles - 1) / n_ctiles;
+    const bool lds_lut = a.N <= 16384;
+    const int64_t rblocks = (p.S + kThreads - 1) / kThreads;
+    int64_t nqb = (2048 + rblocks - 1) / rblocks;  // ~2k blocks
     if (nqb > a.nQ) nqb = a.nQ;
-    if (nqb < 1) nqb = 1;
     const int64_t qb_size = (a.nQ + nqb - 1) / nqb;
     nqb = (a.nQ + qb_size - 1) / qb_size;
-    const int64_t nblocks = n_ctiles * nqb;
-    const int64_t grid = (nblocks + 7) / 8 * 8;
-    if (grid > INT32_MAX) return BS_ERR_ARG;
-    const size_t lds = (size_t)((a.N + 1 + 3) & ~3) * 4 + (size_t)(kThreads / kWave) * kStage * sizeof(Staged);
-    int WC = 64;
-    while (a.W32 % WC) WC >>= 1;
-    ScopedTiming timing("topk_scan", s);
-#define BS_SCAN_CASE(wc)                                                                          \
-  case wc:                                                                                        \
-    hipLaunchKernelGGL((topk_scan_kernel<wc, M>), dim3((unsigned)grid), dim3(kThreads), lds, s, a, \
-                       n_ctiles, nqb, qb_size);                                                   \
-    break;
-    switch (WC) {
-      BS_SCAN_CASE(2)
-      BS_SCAN_CASE(4)
-      BS_SCAN_CASE(8)
-      BS_SCAN_CASE(16)
-      BS_SCAN_CASE(32)
-      BS_SCAN_CASE(64)
-      default:
-        return BS_ERR_ARG;
+    const dim3 g1((unsigned)rblocks, (unsigned)nqb);
+    const size_t l1 = lds_lut ? (size_t)(a.N + 1) * 4 : 0;
+    const int W32 = a.W32;
+#define BS_SAMPLE(w)                                                                                       \
+  do {                                                                                                     \
+    if (lds_lut)                                                                                           \
+      hipLaunchKernelGGL((topk_sample_scores_kernel<M, w, true>), g1, dim3(kThreads), l1, s, a, qb_size);  \
+    else                                                                                                   \
+      hipLaunchKernelGGL((topk_sample_scores_kernel<M, w, false>), g1, dim3(kThreads), l1, s, a, qb_size); \
+  } while (0)
+    switch (W32) {
+      case 2: BS_SAMPLE(2); break;
+      case 4: BS_SAMPLE(4); break;
+      case 8: BS_SAMPLE(8); break;
+      case 16: BS_SAMPLE(16); break;
+      case 32: BS_SAMPLE(32); break;
+      case 64: BS_SAMPLE(64); break;
+      case 128: BS_SAMPLE(128); break;
+      default: BS_SAMPLE(0); break;
     }
-#undef BS_SCAN_CASE
+#undef BS_SAMPLE
+    hipLaunchKernelGGL((topk_sample_select_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), (size_t)p.S * 4, s,
+                       a);
+  }
+  // 2. thresholds, then scan the rest of the corpus
+  if (p.S < a.nC) {
+    {
+      ScopedTiming timing("topk_bound", s);
+      const dim3 g((unsigned)(a.nQp / kWave), (unsigned)((a.N + 1 + kBoundX - 1) / kBoundX));
+      if (a.N <= 16384)
+        hipLaunchKernelGGL((topk_bound_kernel<M, true>), g, dim3(kThreads), (size_t)(a.N + 1) * 4, s, a);
+      else
+        hipLaunchKernelGGL((topk_bound_kernel<M, false>), g, dim3(kThreads), 0, s, a);
+    }
+    const int W32 = a.W32;
+    const bool pow2 = (W32 & (W32 - 1)) == 0;
+    const int qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && W32 == 16) ? 2 : 1);  // queries per lane
+    const int64_t nqb = (a.nQ + kWave - 1) / kWave;                 // 64-query groups
+    const int64_t ngrp = (nqb + qpl - 1) / qpl;                     // waves per slab
+    const int64_t nqb4 = (ngrp + 3) / 4;                            // blocks per slab
+    int64_t n_slabs = (16384 + ngrp - 1) / ngrp;                    // ~16k waves in all
+    if (n_slabs > a.nC) n_slabs = a.nC;
+    const int64_t slab = (a.nC + n_slabs - 1) / n_slabs;
+    n_slabs = (a.nC + slab - 1) / slab;
+    const int64_t grid = n_slabs * nqb4;
+    if (grid > INT32_MAX) return BS_ERR_ARG;
+    ScopedTiming timing("topk_scan", s);
+    const dim3 g((unsigned)grid), b(kThreads);
+    if (pow2 && W32 <= 128) {
+      switch (W32) {
+        case 2: hipLaunchKernelGGL((topk_scan_kernel<2, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 4: hipLaunchKernelGGL((topk_scan_kernel<4, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 8: hipLaunchKernelGGL((topk_scan_kernel<8, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 16: hipLaunchKernelGGL((topk_scan_kernel<16, 2>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 32: hipLaunchKernelGGL((topk_scan_kernel<32, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 64: hipLaunchKernelGGL((topk_scan_kernel<64, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        default: hipLaunchKernelGGL((topk_scan_kernel<128, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+      }
+    } else {
+      int WC = 64;
+      while (W32 % WC) WC >>= 1;
+      switch (WC) {
+        case 2: hipLaunchKernelGGL((topk_scan_generic_kernel<2>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 4: hipLaunchKernelGGL((topk_scan_generic_kernel<4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 8: hipLaunchKernelGGL((topk_scan_generic_kernel<8>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 16: hipLaunchKernelGGL((topk_scan_generic_kernel<16>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 32: hipLaunchKernelGGL((topk_scan_generic_kernel<32>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        default: hipLaunchKernelGGL((topk_scan_generic_kernel<64>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+      }
+    }
   }
   // 3. select
   {
@@ -557,9 +801,10 @@ extern "C" int bs_debug_set_topk_capacity(int64_t cap) {
   return 0;
 }
 
-extern "C" bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, int64_t nC, int32_t N,
-                             int32_t measure, int32_t k, int32_t* out_idx, float* out_score,
-                             void* workspace, size_t workspace_bytes, void* stream) {
+extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint64_t* C,
+                             const int32_t* popC, int64_t nC, int32_t N, int32_t measure, int32_t k,
+                             int32_t* out_idx, float* out_score, void* workspace, size_t workspace_bytes,
+                             void* stream) {
   using namespace bs;
   if (nQ < 0 || nC < 1 || nC > INT32_MAX || !valid_width(N) || k < 1 || k > BS_MAX_K || k > nC ||
       measure < 0 || measure > 3)
@@ -578,15 +823,20 @@ extern "C" bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, i
   a.Q = Q;
   a.C = C;
   a.t32 = reinterpret_cast<const float*>(ws + p.off_t32);
-  a.popQ = reinterpret_cast<const int32_t*>(ws + p.off_popq);
-  a.popC = reinterpret_cast<const int32_t*>(ws + p.off_popc);
+  a.popQ = popQ ? popQ : reinterpret_cast<const int32_t*>(ws + p.off_popq);
+  a.popC = popC ? popC : reinterpret_cast<const int32_t*>(ws + p.off_popc);
+  a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
+  a.skeys = reinterpret_cast<uint32_t*>(ws + p.off_skeys);
+  a.sxab = reinterpret_cast<int32_t*>(ws + p.off_sxab);
   a.qc = reinterpret_cast<QConst*>(ws + p.off_qc);
   a.cnt = reinterpret_cast<int32_t*>(ws + p.off_cnt);
   a.cand = reinterpret_cast<uint64_t*>(ws + p.off_cand);
   a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
+  a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
   a.out_idx = out_idx;
   a.out_score = out_score;
   a.nQ = nQ;
+  a.nQp = (nQ + 63) / 64 * 64;
   a.nC = nC;
   a.S = p.S;
   a.stride = p.stride;
@@ -601,8 +851,8 @@ extern "C" bs_status bs_topk(const uint64_t* Q, int64_t nQ, const uint64_t* C, i
   {
     ScopedTiming timing("topk_prep", s);
     launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
-    launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
-    launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
+    if (!popQ) launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
+    if (!popC) launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
   }
   st = launch_status();
   if (st != BS_OK) return st;

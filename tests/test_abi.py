@@ -73,26 +73,26 @@ def test_pairs_reject_bad_arguments(lib):
     assert lib.bs_and_popcount(FAKE, 1, FAKE, 1, 96, FAKE, None) == 2
     assert lib.bs_and_popcount(FAKE, 2 ** 40, FAKE, 2 ** 40, 64, FAKE, None) == 2
     # estimate: no output requested, bad width, missing or short workspace
-    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, None, None, None, None, FAKE, 1 << 20, None) == 1
-    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 65, FAKE, None, None, None, FAKE, 1 << 20, None) == 2
+    assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, None, None, None, None, FAKE, 1 << 20, None) == 1
+    assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 65, FAKE, None, None, None, FAKE, 1 << 20, None) == 2
     need = lib.bs_estimate_workspace_size(1, 1, 64)
     assert need > 0
-    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, None, need, None) == 3
-    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, FAKE, need - 1, None) == 3
-    assert lib.bs_estimate(FAKE, 1, FAKE, 1, 64, FAKE, None, None, None, P(0x1001), need, None) == 3
+    assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, None, need, None) == 3
+    assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, FAKE, need - 1, None) == 3
+    assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, P(0x1001), need, None) == 3
 
 
 def test_topk_rejects_bad_arguments(lib):
     t = lib.bs_topk
     need = lib.bs_topk_workspace_size(10, 100, 256, 5)
     assert need > 0
-    assert t(None, 10, FAKE, 100, 256, 2, 5, FAKE, None, FAKE, need, None) == 1
-    assert t(FAKE, 10, FAKE, 100, 256, 2, 5, None, None, FAKE, need, None) == 1
-    assert t(FAKE, 10, FAKE, 100, 256, 2, 0, FAKE, None, FAKE, need, None) == 2     # k = 0
-    assert t(FAKE, 10, FAKE, 100, 256, 2, 101, FAKE, None, FAKE, need, None) == 2   # k > nC
-    assert t(FAKE, 10, FAKE, 5000, 256, 2, 1025, FAKE, None, FAKE, need, None) == 2  # k > max
-    assert t(FAKE, 10, FAKE, 100, 256, 4, 5, FAKE, None, FAKE, need, None) == 2     # measure
-    assert t(FAKE, 10, FAKE, 0, 256, 2, 5, FAKE, None, FAKE, need, None) == 2       # empty corpus
-    assert t(FAKE, 10, FAKE, 100, 256, 2, 5, FAKE, None, FAKE, need - 1, None) == 3
+    assert t(None, None, 10, FAKE, None, 100, 256, 2, 5, FAKE, None, FAKE, need, None) == 1
+    assert t(FAKE, None, 10, FAKE, None, 100, 256, 2, 5, None, None, FAKE, need, None) == 1
+    assert t(FAKE, None, 10, FAKE, None, 100, 256, 2, 0, FAKE, None, FAKE, need, None) == 2     # k = 0
+    assert t(FAKE, None, 10, FAKE, None, 100, 256, 2, 101, FAKE, None, FAKE, need, None) == 2   # k > nC
+    assert t(FAKE, None, 10, FAKE, None, 5000, 256, 2, 1025, FAKE, None, FAKE, need, None) == 2  # k > max
+    assert t(FAKE, None, 10, FAKE, None, 100, 256, 4, 5, FAKE, None, FAKE, need, None) == 2     # measure
+    assert t(FAKE, None, 10, FAKE, None, 0, 256, 2, 5, FAKE, None, FAKE, need, None) == 2       # empty corpus
+    assert t(FAKE, None, 10, FAKE, None, 100, 256, 2, 5, FAKE, None, FAKE, need - 1, None) == 3
     assert lib.bs_topk_workspace_size(10, 100, 256, 101) == 0
     assert lib.bs_topk_workspace_size(10, 100, 100, 5) == 0
