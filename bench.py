@@ -67,6 +67,58 @@ def traffic_for(kernel: str, workload: str):
     return rec.get("hbm_bytes_per_launch")
 
 
+def ingest_counters(fetch_dir, write_dir, copy_bytes, N):
+    """HBM bytes per launch of the dominant kernels from rocprofv3 counter runs.
+
+    FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled by the factor that
+    makes the same counter read exactly the known size of a plain copy kernel
+    (the `--copy-bytes` run profiled in the same directory)."""
+    import csv
+    import glob
+
+    copy_bytes = int(copy_bytes)
+
+    def per_kernel(d, counter):
+        out = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                if r["Counter_Name"] != counter:
+                    continue
+                out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return out
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        k = per_kernel(d, counter)
+        copy = [v for name, vals in k.items() if "copy" in name.lower() or "elementwise" in name.lower()
+                for v in vals if v > copy_bytes * 0.25]
+        if not copy:
+            raise SystemExit("no copy-kernel dispatch found in %s" % d)
+        factor = copy_bytes / max(copy)
+        for name, vals in k.items():
+            for short in KERNEL_SOURCES:
+                if short + "_" in name or short + "_lds" in name or name.split("(")[0].endswith(short + "_kernel"):
+                    res.setdefault(short, {})[counter] = (sum(vals) / len(vals), factor, len(vals))
+    out = {}
+    for short, c in res.items():
+        if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+            continue
+        fb, ff, nf = c["FETCH_SIZE"]
+        wb, wf, nw = c["WRITE_SIZE"]
+        out[short] = {"N%d" % N: {"src_sha": src_digest(KERNEL_SOURCES[short]),
+                                  "hbm_bytes_per_launch": fb * ff + wb * wf,
+                                  "fetch_bytes_raw": fb, "fetch_factor": ff, "write_bytes_raw": wb,
+                                  "write_factor": wf, "dispatches": [nf, nw]}}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    old = json.load(open(path)) if os.path.exists(path) else {}
+    for short, v in out.items():
+        old.setdefault(short, {}).update(v)
+    with open(path, "w") as f:
+        json.dump(old, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
 def make_inputs(N_list, dev):
     import torch
 
@@ -103,13 +155,16 @@ class Step:
         self.idx = torch.empty((nQ, k), dtype=torch.int32, device=dev)
         self.score = torch.empty((nQ, k), dtype=torch.float32, device=dev)
         self.ws = bs._workspace(bs.topk_workspace_size(nQ, nC, N, k), dev)
+        self.sws = bs._workspace(bs.sketch_workspace_size(self.pi.numel(), N), dev)
 
     def __call__(self):
         bs, d = self.bs, self.d
-        bs.sketch(d["c_indptr"], d["c_indices"], self.pi, self.N, out=self.C, popcounts=self.popC)
-        bs.sketch(d["q_indptr"], d["q_indices"], self.pi, self.N, out=self.Q, popcounts=self.popQ)
+        bs.sketch(d["c_indptr"], d["c_indices"], self.pi, self.N, out=self.C, popcounts=self.popC,
+                  workspace=self.sws)
+        bs.sketch(d["q_indptr"], d["q_indices"], self.pi, self.N, out=self.Q, popcounts=self.popQ,
+                  workspace=self.sws)
         bs.topk(self.Q, self.C, self.N, "js", self.k, workspace=self.ws, out_idx=self.idx,
-                out_score=self.score)
+                out_score=self.score, popQ=self.popQ, popC=self.popC)
 
 
 def timed(step, steps, warmup):
@@ -130,7 +185,8 @@ def timed(step, steps, warmup):
     bs.timing_enable(False)
     bad = bs.timing_collect()
     kt = {}
-    for name in ["sketch_csr", "topk_prep", "topk_sample", "topk_scan", "topk_select", "topk_fallback"]:
+    for name in ["sketch_pack", "sketch_csr", "topk_prep", "topk_sample", "topk_bound", "topk_scan", "topk_select",
+                 "topk_fallback"]:
         ms, n = bs.timing_get(name)
         if n:
             kt[name] = {"avg_ms": ms / n, "launches": n}
@@ -213,7 +269,15 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=256, help="queries in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many bytes (counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
+                    help="write profiles/traffic.json from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of "
+                         "`bench.py --other-widths ''` (each directory also holding the copy calibration)")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters, N=args.N)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -226,6 +290,14 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_bytes:
+        x = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("copied %d bytes" % args.copy_bytes)
+        return
     others = [int(x) for x in args.other_widths.split(",") if x.strip()]
     widths = [args.N] + [n for n in others if n != args.N]
     corpus, queries, pis, dev_in = make_inputs(widths, dev)

@@ -89,13 +89,21 @@ int32_t bs_words(int32_t N);
  *                                 NULL. The caller clears it; it is never
  *                                 cleared here. When a flag is raised the
  *                                 affected rows are written but undefined.
+ *   workspace  device buffer of bs_sketch_workspace_size(d, N) bytes, 16-byte
+ *              aligned, or NULL. With it, pi is bit-packed there once per call
+ *              and kept in LDS while sketching (when it fits: d*ceil(log2 N)
+ *              bits well under 160 KB); without it, or when the packed map does
+ *              not fit, every pi[i] is gathered from global memory. Both give
+ *              identical sketches.
  * Returns BS_ERR_ARG for a bad size or width, then BS_ERR_NULL for a NULL
  * indptr or pi, a NULL indices with nnz > 0 or a NULL sketches with
  * n_rows > 0 (a pointer to an empty array may be NULL everywhere below).
  */
+size_t bs_sketch_workspace_size(int64_t d, int32_t N);
 bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_rows, int64_t nnz,
                     const int32_t* pi, int64_t d, int32_t N, uint64_t* sketches,
-                    int32_t* popcounts, int32_t* err_flag, void* stream);
+                    int32_t* popcounts, int32_t* err_flag, void* workspace,
+                    size_t workspace_bytes, void* stream);
 
 /*
  * bs_and_popcount — all-pairs sketch inner products
@@ -163,7 +171,8 @@ bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint
  * stream (so it must not be used under graph capture). bs_timing_collect
  * waits for the recorded events and adds each kernel's elapsed time to a
  * per-name total ("sketch_csr", "pair_and_popcount", "pair_estimate",
- * "topk_prep", "topk_sample", "topk_scan", "topk_select", "topk_fallback");
+ * "topk_prep", "topk_sample", "topk_bound", "topk_scan", "topk_select",
+ * "topk_fallback", "sketch_pack");
  * it returns the number of event pairs that could not be read.
  * bs_timing_get returns 1 and the total milliseconds and launch count for a
  * name, or 0 if the name has not been timed. Process-wide, thread-safe.

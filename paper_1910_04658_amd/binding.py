@@ -50,7 +50,9 @@ def load():
             L.bs_status_string.restype = ctypes.c_char_p
             L.bs_words.argtypes = [i32]
             L.bs_words.restype = i32
-            L.bs_sketch.argtypes = [p, p, i64, i64, p, i64, i32, p, p, p, p]
+            L.bs_sketch.argtypes = [p, p, i64, i64, p, i64, i32, p, p, p, p, sz, p]
+            L.bs_sketch_workspace_size.argtypes = [i64, i32]
+            L.bs_sketch_workspace_size.restype = sz
             L.bs_sketch.restype = ctypes.c_int
             L.bs_and_popcount.argtypes = [p, i64, p, i64, i32, p, p]
             L.bs_and_popcount.restype = ctypes.c_int
@@ -116,9 +118,15 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return ws[off:off + max(int(nbytes), 256)]
 
 
+def sketch_workspace_size(d: int, N: int) -> int:
+    return int(load().bs_sketch_workspace_size(int(d), int(N)))
+
+
 def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int,
            out: torch.Tensor | None = None, popcounts: bool | torch.Tensor = True,
-           err_flag: torch.Tensor | None = None):
+           err_flag: torch.Tensor | None = None, workspace: torch.Tensor | None | bool = True):
+    """bs_sketch. workspace: a device buffer of sketch_workspace_size(d, N)
+    bytes, True to allocate one, or None/False for the global-gather path."""
     """bs_sketch: (sketches int64[n][N/64], popcounts int32[n] or None)."""
     _need(indptr, "indptr", torch.int32, 1)
     _need(indices, "indices", torch.int32, 1)
@@ -145,8 +153,15 @@ def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int
         pop = torch.empty(n, dtype=torch.int32, device=dev)
     if err_flag is not None:
         _need(err_flag, "err_flag", torch.int32)
+    if workspace is True:
+        need = sketch_workspace_size(max(pi.numel(), 1), N)
+        workspace = _workspace(need, dev) if need else None
+    elif workspace is False:
+        workspace = None
+    wsn = workspace.numel() if workspace is not None else 0
     st = load().bs_sketch(_ptr(indptr), _ptr(indices if indices.numel() else None), n, indices.numel(),
-                          _ptr(pi), pi.numel(), int(N), _ptr(out), _ptr(pop), _ptr(err_flag), _stream())
+                          _ptr(pi), pi.numel(), int(N), _ptr(out), _ptr(pop), _ptr(err_flag),
+                          _ptr(workspace), wsn, _stream())
     _check(st, "bs_sketch")
     return out, pop
 

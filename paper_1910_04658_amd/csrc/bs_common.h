@@ -13,6 +13,10 @@ constexpr int kWave = 64;  // CDNA wavefront width
 // Returns BS_OK if the current device is a gfx950, else BS_ERR_DEVICE.
 bs_status check_device();
 
+// LDS bytes a block may use and the compute-unit count of the current device
+// (cached per device; zeros if the runtime cannot say).
+void device_limits(int* lds_max, int* n_cu);
+
 inline bool valid_width(int32_t N) { return N >= 64 && N <= BS_MAX_N && N % 64 == 0; }
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }

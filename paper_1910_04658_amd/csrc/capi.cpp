@@ -51,6 +51,30 @@ ScopedTiming::~ScopedTiming() {
   g_pending.push_back(Pending{name_, start_, stop_});
 }
 
+void device_limits(int* lds_max, int* n_cu) {
+  static std::mutex mu;
+  static int cache[64][2];
+  static bool have[64] = {false};
+  int dev = 0;
+  *lds_max = 0;
+  *n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[dev]) {
+    int l = 0, c = 0;
+    if (hipDeviceGetAttribute(&l, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      l = 0;
+      c = 0;
+    }
+    cache[dev][0] = l;
+    cache[dev][1] = c;
+    have[dev] = true;
+  }
+  *lds_max = cache[dev][0];
+  *n_cu = cache[dev][1];
+}
+
 bs_status check_device() {
   static std::mutex mu;
   static int known[64] = {0};  // 0 unknown, 1 gfx950, 2 other

@@ -141,13 +141,210 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_csr_kernel(Sket
   if (a.err && errbits) atomicOr(a.err, (int32_t)errbits);
 }
 
+// ---- map-in-LDS variant ---------------------------------------------------
+// When pi fits in LDS bit-packed (ceil(log2 N) bits per entry), it is packed
+// once per call into the caller's workspace, and a persistent grid of one
+// 16-wave block per CU copies it into LDS, so every gather is an LDS read
+// plus a funnel shift instead of a 128-byte L2 line fill for 4 useful bytes.
+// Each wave then owns a contiguous range of rows, processed in windows of G
+// rows exactly as above.
+constexpr int kBigBlockWaves = 16;
+constexpr int kUnrollLds = 16;  // element loads in flight per lane
+
+struct SketchLdsArgs {
+  SketchArgs s;
+  const uint32_t* __restrict__ packed;  // bit-packed map (table_words - 1 words)
+  int32_t bits;         // bits per packed map entry
+  int32_t table_words;  // packed map words in LDS (including one pad word)
+  int64_t n_windows;
+};
+
+// Bit-pack pi: entry e occupies bits [e*bits, (e+1)*bits) of the packed
+// words, so the 32 entries of group g fill exactly words [g*bits, (g+1)*bits).
+// One thread per group: no division and no atomics. Out-of-range values are
+// reported and stored as 0, so the packed table always holds valid targets.
+__global__ void pack_map_kernel(const int32_t* __restrict__ pi, int64_t d, int32_t N, int32_t bits,
+                                uint32_t* __restrict__ packed, int32_t* __restrict__ err) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_groups = (d + 31) / 32;
+  if (gi >= n_groups) return;
+  const int64_t e0 = gi * 32;
+  uint32_t v[32];
+  if (e0 + 32 <= d && (reinterpret_cast<uintptr_t>(pi) & 15) == 0) {  // eight 16-byte loads
+    const int4* src = reinterpret_cast<const int4*>(pi + e0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int4 q = src[u];
+      v[4 * u] = (uint32_t)q.x;
+      v[4 * u + 1] = (uint32_t)q.y;
+      v[4 * u + 2] = (uint32_t)q.z;
+      v[4 * u + 3] = (uint32_t)q.w;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 32; ++u) v[u] = e0 + u < d ? (uint32_t)pi[e0 + u] : 0u;
+  }
+  uint64_t acc = 0;
+  int fill = 0;
+  uint32_t* dst = packed + gi * bits;
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    uint32_t x = v[u];
+    if (x >= (uint32_t)N) {
+      bad = true;
+      x = 0;
+    }
+    acc |= (uint64_t)x << fill;
+    fill += bits;
+    if (fill >= 32) {
+      *dst++ = (uint32_t)acc;
+      acc >>= 32;
+      fill -= 32;
+    }
+  }
+  if (bad && err) atomicOr(err, (int32_t)BS_FLAG_MAP);
+}
+
+__global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(SketchLdsArgs A) {
+  extern __shared__ uint32_t lds[];
+  const SketchArgs& a = A.s;
+  const int bits = A.bits;
+  uint32_t* table = lds;
+  uint32_t* stage_base = lds + A.table_words;
+  const uint32_t emask = (1u << bits) - 1u;
+
+  // 1. copy the packed map (built by pack_map_kernel) into LDS, 16 bytes per
+  //    load, then clear the pad word read past the last entry.
+  uint32_t errbits = 0;
+  {
+    const int n16 = (A.table_words - 1) / 4;  // whole 16-byte chunks of the packed words
+    const uint4* src = reinterpret_cast<const uint4*>(A.packed);
+    uint4* dst = reinterpret_cast<uint4*>(table);
+    for (int t = threadIdx.x; t < n16; t += blockDim.x) dst[t] = src[t];
+    for (int t = n16 * 4 + threadIdx.x; t < A.table_words - 1; t += blockDim.x) table[t] = A.packed[t];
+    if (threadIdx.x == 0) table[A.table_words - 1] = 0u;
+  }
+  __syncthreads();
+
+  // 2. each wave owns a contiguous range of rows, in windows of G rows
+  const int wid = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int W32 = a.W32;
+  uint32_t* sk = stage_base + (size_t)wid * a.stride;
+  uint32_t* cnt = sk + (size_t)a.G * W32;
+  const uint32_t d32 = (uint32_t)a.d;
+  const int64_t total_waves = (int64_t)gridDim.x * kBigBlockWaves;
+  const int64_t per_wave = (a.n_rows + total_waves - 1) / total_waves;
+  const int64_t wv = (int64_t)blockIdx.x * kBigBlockWaves + wid;
+  const int64_t rw0 = wv * per_wave;
+  const int64_t rw1 = rw0 + per_wave < a.n_rows ? rw0 + per_wave : a.n_rows;
+
+  int32_t p_next = 0;
+  if (rw0 < rw1) {
+    const int g0 = (int)(rw1 - rw0 < a.G ? rw1 - rw0 : a.G);
+    p_next = (lane <= g0) ? a.indptr[rw0 + lane] : 0;
+  }
+  for (int64_t r0 = rw0; r0 < rw1; r0 += a.G) {
+    const int g = (int)(rw1 - r0 < a.G ? rw1 - r0 : a.G);
+    const int32_t p = p_next;
+    {  // row pointers of the next window, in flight while this one runs
+      const int64_t r1 = r0 + a.G;
+      const int gn = (int)(rw1 - r1 < a.G ? rw1 - r1 : a.G);
+      p_next = (r1 < rw1 && lane <= gn) ? a.indptr[r1 + lane] : 0;
+    }
+    const int32_t prev = __shfl_up(p, 1);
+    const bool bad = (lane <= g) && (p < 0 || (int64_t)p > a.nnz || (lane >= 1 && p < prev) ||
+                                     (r0 == 0 && lane == 0 && p != 0));
+    const bool window_bad = __ballot(bad) != 0;
+    for (int w = lane; w < g * W32; w += kWave) sk[w] = 0u;
+    if (lane < g) cnt[lane] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (window_bad) errbits |= BS_FLAG_INDPTR;
+    if (!window_bad) {
+      const int64_t e0 = __builtin_amdgcn_readfirstlane(p);
+      const int64_t e1 = __builtin_amdgcn_readlane(p, g);
+      int cur = 0;
+      int64_t nxt = (g > 1) ? (int64_t)__builtin_amdgcn_readlane(p, 1) : INT64_MAX;
+      for (int64_t base = e0; base < e1; base += (int64_t)kWave * kUnrollLds) {
+        int32_t idx[kUnrollLds];
+#pragma unroll
+        for (int u = 0; u < kUnrollLds; ++u) {
+          const int64_t k = base + u * kWave + lane;
+          idx[u] = (k < e1) ? __builtin_nontemporal_load(a.indices + k) : -1;
+        }
+        int rowv[kUnrollLds];
+#pragma unroll
+        for (int u = 0; u < kUnrollLds; ++u) rowv[u] = cur;
+        const int64_t end = base + (int64_t)kWave * kUnrollLds;
+        while (nxt < end) {
+#pragma unroll
+          for (int u = 0; u < kUnrollLds; ++u) rowv[u] += (base + u * kWave + lane >= nxt) ? 1 : 0;
+          ++cur;
+          nxt = (cur + 1 < g) ? (int64_t)__builtin_amdgcn_readlane(p, cur + 1) : INT64_MAX;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnrollLds; ++u) {
+          const int64_t k = base + u * kWave + lane;
+          if (k < e1) {
+            if ((uint32_t)idx[u] < d32) {
+              const uint32_t bp = (uint32_t)idx[u] * (uint32_t)bits;
+              const uint32_t lo = table[bp >> 5], hi = table[(bp >> 5) + 1];
+              const uint32_t j = __builtin_amdgcn_alignbit(hi, lo, bp & 31) & emask;
+              atomicOr(&sk[rowv[u] * W32 + (j >> 5)], 1u << (j & 31));
+            } else {
+              errbits |= BS_FLAG_INDEX;
+            }
+          }
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int W64 = W32 / 2;
+    const uint64_t* s64 = reinterpret_cast<const uint64_t*>(sk);
+    uint64_t* o64 = reinterpret_cast<uint64_t*>(a.out32 + (size_t)r0 * W32);
+    for (int w = lane; w < g * W64; w += kWave) {
+      const uint64_t v = s64[w];
+      __builtin_nontemporal_store(v, o64 + w);
+      if (a.pop) atomicAdd(&cnt[w / W64], (uint32_t)__builtin_popcountll(v));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (a.pop && lane < g) a.pop[r0 + lane] = (int32_t)cnt[lane];
+  }
+  if (a.err && errbits) atomicOr(a.err, (int32_t)errbits);
+}
+
 }  // namespace
 }  // namespace bs
+
+namespace bs {
+namespace {
+// Packed-map geometry for (d, N); table_words includes one pad word.
+inline int map_bits(int32_t N) {
+  int bits = 1;
+  while ((1LL << bits) < (long long)N) ++bits;
+  return bits;
+}
+inline int64_t map_table_words(int64_t d, int32_t N) { return (d + 31) / 32 * map_bits(N) + 1; }
+}  // namespace
+}  // namespace bs
+
+extern "C" size_t bs_sketch_workspace_size(int64_t d, int32_t N) {
+  using namespace bs;
+  if (d < 1 || d > INT32_MAX || !valid_width(N)) return 0;
+  return align256((size_t)map_table_words(d, N) * 4);
+}
 
 extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_rows,
                                int64_t nnz, const int32_t* pi, int64_t d, int32_t N,
                                uint64_t* sketches, int32_t* popcounts, int32_t* err_flag,
-                               void* stream) {
+                               void* workspace, size_t workspace_bytes, void* stream) {
   using namespace bs;
   if (n_rows < 0 || nnz < 0 || nnz > INT32_MAX || d < 1 || d > INT32_MAX || !valid_width(N))
     return BS_ERR_ARG;
@@ -155,6 +352,58 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
   bs_status st = check_device();
   if (st != BS_OK) return st;
   if (n_rows == 0) return BS_OK;
+
+  // Map-in-LDS path when the bit-packed map leaves room for staging.
+  int lds_max = 0, n_cu = 0;
+  device_limits(&lds_max, &n_cu);
+  const int bits = map_bits(N);
+  const int64_t table_words = map_table_words(d, N);
+  const int64_t W32 = N / 32;
+  const int64_t table_bytes = table_words * 4;
+  const int64_t stage_bytes_per_wave = ((int64_t)lds_max - table_bytes) / kBigBlockWaves;
+  int64_t Gl = stage_bytes_per_wave / (4 * (W32 + 1));
+  if (Gl > 16) Gl = 16;
+  const bool have_ws = workspace && workspace_bytes >= (size_t)table_words * 4 &&
+                       (reinterpret_cast<uintptr_t>(workspace) & 15) == 0;
+  if (have_ws && n_cu > 0 && Gl >= 1 && table_words < (INT64_C(1) << 26)) {
+    SketchLdsArgs L;
+    L.s.indptr = indptr;
+    L.s.indices = indices;
+    L.s.pi = pi;
+    L.s.out32 = reinterpret_cast<uint32_t*>(sketches);
+    L.s.pop = popcounts;
+    L.s.err = err_flag;
+    L.s.n_rows = n_rows;
+    L.s.nnz = nnz;
+    L.s.d = d;
+    L.s.N = N;
+    L.s.W32 = (int32_t)W32;
+    L.s.G = (int32_t)Gl;
+    L.s.stride = (int32_t)(Gl * W32 + Gl);
+    L.bits = bits;
+    L.packed = static_cast<const uint32_t*>(workspace);
+    L.table_words = (int32_t)table_words;
+    L.n_windows = (n_rows + Gl - 1) / Gl;
+    const size_t lds = (size_t)table_bytes + (size_t)kBigBlockWaves * L.s.stride * 4;
+    // one block per CU; fewer when there are fewer than ~2 windows per wave
+    int64_t grid = (L.n_windows + 2 * kBigBlockWaves - 1) / (2 * kBigBlockWaves);
+    if (grid > n_cu) grid = n_cu;
+    if (grid < 1) grid = 1;
+    if ((size_t)lds <= (size_t)lds_max) {
+      if (lds > 65536) (void)hipFuncSetAttribute((const void*)sketch_csr_lds_kernel,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      {
+        const int64_t n_groups = (d + 31) / 32;
+        ScopedTiming timing("sketch_pack", as_stream(stream));
+        hipLaunchKernelGGL(pack_map_kernel, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0,
+                           as_stream(stream), pi, d, N, bits, static_cast<uint32_t*>(workspace), err_flag);
+      }
+      ScopedTiming timing("sketch_csr", as_stream(stream));
+      hipLaunchKernelGGL(sketch_csr_lds_kernel, dim3((unsigned)grid), dim3(kBigBlockWaves * kWave), lds,
+                         as_stream(stream), L);
+      return launch_status();
+    }
+  }
 
   SketchArgs a;
   a.indptr = indptr;

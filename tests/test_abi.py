@@ -55,16 +55,16 @@ FAKE = P(0x1000)  # never dereferenced: every call below fails host-side validat
 
 def test_sketch_rejects_bad_arguments(lib):
     s = lib.bs_sketch
-    assert s(None, FAKE, 1, 1, FAKE, 10, 64, FAKE, None, None, None) == 1
-    assert s(FAKE, None, 1, 5, FAKE, 10, 64, FAKE, None, None, None) == 1
-    assert s(FAKE, FAKE, 1, 1, None, 10, 64, FAKE, None, None, None) == 1
-    assert s(FAKE, FAKE, 1, 1, FAKE, 10, 64, None, None, None, None) == 1
-    assert s(FAKE, FAKE, -1, 1, FAKE, 10, 64, FAKE, None, None, None) == 2
-    assert s(FAKE, FAKE, 1, -1, FAKE, 10, 64, FAKE, None, None, None) == 2
-    assert s(FAKE, FAKE, 1, 2 ** 31, FAKE, 10, 64, FAKE, None, None, None) == 2
-    assert s(FAKE, FAKE, 1, 1, FAKE, 0, 64, FAKE, None, None, None) == 2
+    assert s(None, FAKE, 1, 1, FAKE, 10, 64, FAKE, None, None, None, 0, None) == 1
+    assert s(FAKE, None, 1, 5, FAKE, 10, 64, FAKE, None, None, None, 0, None) == 1
+    assert s(FAKE, FAKE, 1, 1, None, 10, 64, FAKE, None, None, None, 0, None) == 1
+    assert s(FAKE, FAKE, 1, 1, FAKE, 10, 64, None, None, None, None, 0, None) == 1
+    assert s(FAKE, FAKE, -1, 1, FAKE, 10, 64, FAKE, None, None, None, 0, None) == 2
+    assert s(FAKE, FAKE, 1, -1, FAKE, 10, 64, FAKE, None, None, None, 0, None) == 2
+    assert s(FAKE, FAKE, 1, 2 ** 31, FAKE, 10, 64, FAKE, None, None, None, 0, None) == 2
+    assert s(FAKE, FAKE, 1, 1, FAKE, 0, 64, FAKE, None, None, None, 0, None) == 2
     for N in [0, 63, 100, 65536 + 64]:
-        assert s(FAKE, FAKE, 1, 1, FAKE, 10, N, FAKE, None, None, None) == 2
+        assert s(FAKE, FAKE, 1, 1, FAKE, 10, N, FAKE, None, None, None, 0, None) == 2
 
 
 def test_pairs_reject_bad_arguments(lib):

@@ -9,21 +9,25 @@ from helpers import to_dev, words_np
 pytestmark = pytest.mark.gpu
 
 
-def run_sketch(csr, pi, N, dev, err=False):
+def run_sketch(csr, pi, N, dev, err=False, workspace=True):
+    """workspace=True: map packed into a workspace and kept in LDS (when it
+    fits); workspace=False: every map entry gathered from global memory."""
     import torch
     from paper_1910_04658_amd import binding as bs
     flag = torch.zeros(1, dtype=torch.int32, device=dev) if err else None
-    w, p = bs.sketch(to_dev(csr.indptr, dev), to_dev(csr.indices, dev), to_dev(pi, dev), N, err_flag=flag)
+    w, p = bs.sketch(to_dev(csr.indptr, dev), to_dev(csr.indices, dev), to_dev(pi, dev), N, err_flag=flag,
+                     workspace=workspace)
     torch.cuda.synchronize()
     return words_np(w), p.cpu().numpy(), (int(flag.item()) if err else None)
 
 
 def check(csr, pi, N, dev):
-    gw, gp, flag = run_sketch(csr, pi, N, dev, err=True)
     ow, op = oracle.sketch(csr.indptr, csr.indices, csr.d, pi, N)
-    assert flag == 0
-    assert np.array_equal(gw, ow)
-    assert np.array_equal(gp, op)
+    for ws in (True, False):
+        gw, gp, flag = run_sketch(csr, pi, N, dev, err=True, workspace=ws)
+        assert flag == 0
+        assert np.array_equal(gw, ow), "sketch words differ (workspace=%s)" % ws
+        assert np.array_equal(gp, op), "popcounts differ (workspace=%s)" % ws
 
 
 def test_small_corpus_N1024(dev):
@@ -96,19 +100,20 @@ def test_error_flags(dev):
     bounds checks keep every access in bounds."""
     d, N = 100, 128
     pi = datagen.random_map(d, N, 1)
-    c = datagen.from_rows([[1, 2], [5, 100], [3]], d)  # index 100 >= d
-    _, _, flag = run_sketch(c, pi, N, dev, err=True)
-    assert flag & 2
-    pi_bad = pi.copy()
-    pi_bad[7] = N  # map value out of range
-    c = datagen.from_rows([[1, 7], [3]], d)
-    _, _, flag = run_sketch(c, pi_bad, N, dev, err=True)
-    assert flag & 4
-    c = datagen.from_rows([[1, 2], [3, 4]], d)
-    c.indptr[1] = 3  # not non-decreasing: 0, 3, 4 -> ok; make 0, 3, 2
-    c.indptr[2] = 2
-    _, _, flag = run_sketch(c, pi, N, dev, err=True)
-    assert flag & 1
+    for ws in (True, False):
+        c = datagen.from_rows([[1, 2], [5, 100], [3]], d)  # index 100 >= d
+        _, _, flag = run_sketch(c, pi, N, dev, err=True, workspace=ws)
+        assert flag & 2
+        pi_bad = pi.copy()
+        pi_bad[7] = N  # map value out of range
+        c = datagen.from_rows([[1, 7], [3]], d)
+        _, _, flag = run_sketch(c, pi_bad, N, dev, err=True, workspace=ws)
+        assert flag & 4
+        c = datagen.from_rows([[1, 2], [3, 4]], d)
+        c.indptr[2] = 2  # 0, 2, 2 is fine; 0, 3, 2 is not non-decreasing
+        c.indptr[1] = 3
+        _, _, flag = run_sketch(c, pi, N, dev, err=True, workspace=ws)
+        assert flag & 1
 
 
 @pytest.mark.parametrize("N", [256, 1024, 4096])
