@@ -299,3 +299,83 @@ def planted_pairs(rng: np.random.Generator, base: CSR, frac: np.ndarray, s: floa
                         break
         rows.append(np.sort(np.asarray(kept + new, dtype=np.int64)))
     return from_rows(rows, d)
+
+
+# ---------------------------------------------------------------------------
+# Pairs with known Jaccard similarity (training data for a learned estimator)
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class PairSet:
+    """Vectors (CSR) and index pairs into them with their exact Jaccard similarity."""
+
+    csr: CSR
+    ia: np.ndarray      # int32[n_pairs]
+    ib: np.ndarray      # int32[n_pairs]
+    inter: np.ndarray   # int32[n_pairs] |a n b|
+    jaccard: np.ndarray  # float64[n_pairs] |a n b| / |a u b| (0 for two empty sets)
+
+
+def variant_groups(n_groups: int, group_size: int, d: int = 100_000, mean: float = 230.0, sd: float = 150.0,
+                   s: float = 1.1, seed: int = 4004) -> PairSet:
+    """Groups of near-duplicate vectors and all pairs inside each group.
+
+    Each group starts from a base vector (row lengths round(lognormal(mean, sd)),
+    Zipf(s) ids, as `lognormal_corpus`). Each of its `group_size` members keeps
+    every base id with probability 1 - f and adds round(f * |base|) fresh
+    Zipf(s) ids, f ~ U(0, 1) drawn per member, so pair similarities cover [0, 1].
+    Every unordered pair of members of a group is listed, with its exact
+    intersection size and Jaccard similarity (set arithmetic on the ids).
+    """
+    rng = np.random.default_rng(seed)
+    base = lognormal_corpus(n_groups, d=d, mean=mean, sd=sd, seed=int(rng.integers(1 << 62)))
+    G = group_size
+    blen = base.lengths()
+    cdf = np.cumsum(np.arange(1, d + 1, dtype=np.float64) ** -s)
+    cdf /= cdf[-1]
+    perm = rng.permutation(d).astype(np.int64)
+    n_mem = n_groups * G
+    f = rng.random(n_mem)
+    mem_group = np.repeat(np.arange(n_groups), G)
+    # kept base ids
+    reps = blen[mem_group]
+    starts = base.indptr[:-1].astype(np.int64)[mem_group]
+    off = np.arange(int(reps.sum()), dtype=np.int64) - np.repeat(np.cumsum(reps) - reps, reps)
+    kept_ids = base.indices.astype(np.int64)[np.repeat(starts, reps) + off]
+    kept_mem = np.repeat(np.arange(n_mem), reps)
+    keep = rng.random(len(kept_ids)) >= np.repeat(f, reps)
+    # fresh ids
+    n_new = np.rint(f * blen[mem_group]).astype(np.int64)
+    new_ids = perm[np.searchsorted(cdf, rng.random(int(n_new.sum())), side="right").clip(0, d - 1)]
+    new_mem = np.repeat(np.arange(n_mem), n_new)
+    mem = np.concatenate([kept_mem[keep], new_mem])
+    ids = np.concatenate([kept_ids[keep], new_ids])
+    key = np.unique(mem * d + ids)
+    mem_u = key // d
+    ids_u = (key % d).astype(np.int32)
+    counts = np.bincount(mem_u, minlength=n_mem)
+    indptr = np.zeros(n_mem + 1, np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    if indptr[-1] >= 2 ** 31:
+        raise ValueError("too many set bits for one int32 CSR batch")
+    csr = CSR(indptr.astype(np.int32), ids_u, d)
+    # exact intersections inside each group: dense 0/1 matrix over the group's ids
+    iu, ju = np.triu_indices(G, 1)
+    ia = np.empty(n_groups * len(iu), np.int32)
+    ib = np.empty_like(ia)
+    inter = np.empty_like(ia)
+    for g in range(n_groups):
+        lo, hi = indptr[g * G], indptr[(g + 1) * G]
+        local, inv = np.unique(ids_u[lo:hi], return_inverse=True)
+        M = np.zeros((G, len(local)), np.float32)
+        M[np.repeat(np.arange(G), counts[g * G:(g + 1) * G]), inv] = 1.0
+        I = M @ M.T
+        sl = slice(g * len(iu), (g + 1) * len(iu))
+        ia[sl] = g * G + iu
+        ib[sl] = g * G + ju
+        inter[sl] = I[iu, ju].astype(np.int32)
+    la = counts[ia].astype(np.float64)
+    lb = counts[ib].astype(np.float64)
+    union = la + lb - inter
+    jac = np.where(union > 0, inter / np.maximum(union, 1), 0.0)
+    return PairSet(csr, ia, ib, inter, jac)

@@ -166,6 +166,55 @@ bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint
                   void* stream);
 
 /*
+ * bs_pair_popcount — <a_s, b_s> = |A[ia[i]] AND B[ib[i]]| (Algorithm 1,
+ * second step) for a list of n_pairs row pairs.
+ *   ia, ib    int32[n_pairs] row indices into A (nA rows) and B (nB rows).
+ *   out       int32[n_pairs].
+ *   err_flag  int32[1] or NULL: set to 1 (atomic OR) if an index is out of
+ *             range; that pair's output is 0.
+ */
+bs_status bs_pair_popcount(const uint64_t* A, int64_t nA, const int32_t* ia, const uint64_t* B,
+                           int64_t nB, const int32_t* ib, int64_t n_pairs, int32_t N, int32_t* out,
+                           int32_t* err_flag, void* stream);
+
+/*
+ * Learned Jaccard estimator (an extension built on Algorithms 1-3, not in
+ * the paper): a 4 -> 64 -> 64 -> 1 ReLU network with BF16 weights and FP32
+ * accumulation, run on the vector ALU (first and last layer) and the matrix
+ * cores (64 x 64 layer, v_mfma_f32_16x16x16_bf16), that predicts
+ *   p = JS_closed(x_a, x_b, x_ab, N) + MLP(x_a/N, x_b/N, x_ab/N, log2(N)/16)
+ * from the three sketch counts of a pair, JS_closed being the FP32 Jaccard
+ * estimate of bs_topk. An all-zero output layer gives the closed form.
+ * Parameters: bs_mlp_param_count() = 4545 values, in this order:
+ *   W1[64][4], b1[64], W2[64][64] (row = output unit), b2[64], w3[64], b3.
+ *   w        uint16[4545]  BF16 bit patterns of the parameters.
+ *   xa, xb, xab  int32[n]  |a_s|, |b_s|, |a_s AND b_s| of each pair.
+ *   workspace    >= bs_mlp_workspace_size(n, N) bytes, 256-byte aligned.
+ * bs_mlp_forward: out[i] = clamp(p_i, 0, 1) (float[n]).
+ * bs_mlp_grad: the mean squared error against label (float[n], exact
+ *   Jaccard) in *loss (float, may be NULL) and its gradient with respect to
+ *   the parameters in grad (float[4545]); deterministic (fixed-order sums).
+ * bs_mlp_train_step: the same gradient, then one Adam step (beta1 0.9,
+ *   beta2 0.999, eps 1e-8, bias-corrected for 1-based `step`) on the FP32
+ *   master copy `master` (float[4545]) with moments adam_m, adam_v
+ *   (float[4545], zero before step 1), and w refreshed as BF16(master).
+ * bs_mlp_to_bf16: w = BF16(master), round to nearest even.
+ */
+int32_t bs_mlp_param_count(void);
+size_t bs_mlp_workspace_size(int64_t n, int32_t N);
+bs_status bs_mlp_forward(const uint16_t* w, const int32_t* xa, const int32_t* xb, const int32_t* xab,
+                         int64_t n, int32_t N, float* out, void* workspace, size_t workspace_bytes,
+                         void* stream);
+bs_status bs_mlp_grad(const uint16_t* w, const int32_t* xa, const int32_t* xb, const int32_t* xab,
+                      const float* label, int64_t n, int32_t N, float* grad, float* loss,
+                      void* workspace, size_t workspace_bytes, void* stream);
+bs_status bs_mlp_train_step(float* master, uint16_t* w, float* adam_m, float* adam_v, int64_t step,
+                            float lr, const int32_t* xa, const int32_t* xb, const int32_t* xab,
+                            const float* label, int64_t n, int32_t N, float* loss, void* workspace,
+                            size_t workspace_bytes, void* stream);
+bs_status bs_mlp_to_bf16(const float* master, uint16_t* w, void* stream);
+
+/*
  * Kernel timing for benchmarks and profiling (off by default). While enabled,
  * every launch is bracketed by two HIP events recorded on the caller's
  * stream (so it must not be used under graph capture). bs_timing_collect

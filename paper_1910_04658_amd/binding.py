@@ -71,6 +71,19 @@ def load():
             L.bs_timing_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_int64)]
             L.bs_timing_get.restype = ctypes.c_int
+            L.bs_pair_popcount.argtypes = [p, i64, p, p, i64, p, i64, i32, p, p, p]
+            L.bs_pair_popcount.restype = ctypes.c_int
+            L.bs_mlp_param_count.restype = i32
+            L.bs_mlp_workspace_size.argtypes = [i64, i32]
+            L.bs_mlp_workspace_size.restype = sz
+            L.bs_mlp_forward.argtypes = [p, p, p, p, i64, i32, p, p, sz, p]
+            L.bs_mlp_forward.restype = ctypes.c_int
+            L.bs_mlp_grad.argtypes = [p, p, p, p, p, i64, i32, p, p, p, sz, p]
+            L.bs_mlp_grad.restype = ctypes.c_int
+            L.bs_mlp_train_step.argtypes = [p, p, p, p, i64, ctypes.c_float, p, p, p, p, i64, i32, p, p, sz, p]
+            L.bs_mlp_train_step.restype = ctypes.c_int
+            L.bs_mlp_to_bf16.argtypes = [p, p, p]
+            L.bs_mlp_to_bf16.restype = ctypes.c_int
             L.bs_debug_set_topk_capacity.argtypes = [i64]
             L.bs_debug_set_topk_capacity.restype = ctypes.c_int
             _lib = L
@@ -277,3 +290,82 @@ def timing_get(name: str):
     n = ctypes.c_int64(0)
     load().bs_timing_get(name.encode(), ctypes.byref(ms), ctypes.byref(n))
     return ms.value, n.value
+
+
+def pair_popcount(A: torch.Tensor, ia: torch.Tensor, B: torch.Tensor, ib: torch.Tensor, N: int,
+                  out: torch.Tensor | None = None, err_flag: torch.Tensor | None = None):
+    """bs_pair_popcount: int32[n] of |A[ia[i]] AND B[ib[i]]|."""
+    _need(A, "A", torch.int64, 2)
+    _need(B, "B", torch.int64, 2)
+    _need(ia, "ia", torch.int32, 1)
+    _need(ib, "ib", torch.int32, 1)
+    if ia.numel() != ib.numel():
+        raise ValueError("ia and ib must have the same length")
+    if out is None:
+        out = torch.empty(ia.numel(), dtype=torch.int32, device=A.device)
+    st = load().bs_pair_popcount(_ptr(A), A.shape[0], _ptr(ia), _ptr(B), B.shape[0], _ptr(ib), ia.numel(),
+                                 int(N), _ptr(out), _ptr(err_flag), _stream())
+    _check(st, "bs_pair_popcount")
+    return out
+
+
+def mlp_param_count() -> int:
+    return int(load().bs_mlp_param_count())
+
+
+def mlp_workspace(n: int, N: int, device) -> torch.Tensor:
+    return _workspace(load().bs_mlp_workspace_size(int(n), int(N)), device)
+
+
+def _counts(xa, xb, xab):
+    for t, nm in ((xa, "xa"), (xb, "xb"), (xab, "xab")):
+        _need(t, nm, torch.int32, 1)
+    if not (xa.numel() == xb.numel() == xab.numel()):
+        raise ValueError("xa, xb, xab must have the same length")
+    return xa.numel()
+
+
+def mlp_forward(w_bf16: torch.Tensor, xa, xb, xab, N: int, out=None, workspace=None):
+    """bs_mlp_forward: learned Jaccard estimates, float32[n]."""
+    _need(w_bf16, "w", torch.int16, 1)
+    n = _counts(xa, xb, xab)
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=xa.device)
+    if workspace is None:
+        workspace = mlp_workspace(n, N, xa.device)
+    st = load().bs_mlp_forward(_ptr(w_bf16), _ptr(xa), _ptr(xb), _ptr(xab), n, int(N), _ptr(out),
+                               _ptr(workspace), workspace.numel(), _stream())
+    _check(st, "bs_mlp_forward")
+    return out
+
+
+def mlp_grad(w_bf16: torch.Tensor, xa, xb, xab, label: torch.Tensor, N: int, workspace=None):
+    """bs_mlp_grad: (grad float32[4545], loss float32[1])."""
+    _need(w_bf16, "w", torch.int16, 1)
+    _need(label, "label", torch.float32, 1)
+    n = _counts(xa, xb, xab)
+    grad = torch.empty(mlp_param_count(), dtype=torch.float32, device=xa.device)
+    loss = torch.empty(1, dtype=torch.float32, device=xa.device)
+    if workspace is None:
+        workspace = mlp_workspace(n, N, xa.device)
+    st = load().bs_mlp_grad(_ptr(w_bf16), _ptr(xa), _ptr(xb), _ptr(xab), _ptr(label), n, int(N), _ptr(grad),
+                            _ptr(loss), _ptr(workspace), workspace.numel(), _stream())
+    _check(st, "bs_mlp_grad")
+    return grad, loss
+
+
+def mlp_train_step(master, w_bf16, adam_m, adam_v, step: int, lr: float, xa, xb, xab, label, N: int,
+                   loss=None, workspace=None):
+    """bs_mlp_train_step (in place on master, w_bf16, adam_m, adam_v)."""
+    n = _counts(xa, xb, xab)
+    if workspace is None:
+        workspace = mlp_workspace(n, N, xa.device)
+    st = load().bs_mlp_train_step(_ptr(master), _ptr(w_bf16), _ptr(adam_m), _ptr(adam_v), int(step), float(lr),
+                                  _ptr(xa), _ptr(xb), _ptr(xab), _ptr(label), n, int(N), _ptr(loss),
+                                  _ptr(workspace), workspace.numel(), _stream())
+    _check(st, "bs_mlp_train_step")
+
+
+def mlp_to_bf16(master: torch.Tensor, w_bf16: torch.Tensor):
+    st = load().bs_mlp_to_bf16(_ptr(master), _ptr(w_bf16), _stream())
+    _check(st, "bs_mlp_to_bf16")

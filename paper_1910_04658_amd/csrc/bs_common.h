@@ -72,4 +72,23 @@ __device__ __forceinline__ float key_float(uint32_t k) {
   return __uint_as_float(u);
 }
 
+// The estimators of Algorithms 1-4 in FP32 from table values T(x_a), T(x_b),
+// T(x_u), with Hamming as |a|+|b|-2 IP, in the canonical operation order:
+// s = Ta + Tb, ip = s - Tu, ham = s - 2 ip, js = ip / (ip + ham),
+// cos = ip / sqrt(Ta Tb); zero denominators give 0.
+template <int M>
+__device__ __forceinline__ float score_f32(float Ta, float Tb, float Tu) {
+  const float s = Ta + Tb;
+  const float ip = s - Tu;
+  if (M == BS_IP) return ip;
+  const float ham = s - (ip + ip);
+  if (M == BS_HAMMING) return ham;
+  if (M == BS_JACCARD) {
+    const float den = ip + ham;
+    return den == 0.0f ? 0.0f : ip / den;
+  }
+  const float pr = Ta * Tb;
+  return pr == 0.0f ? 0.0f : ip / sqrtf(pr);
+}
+
 }  // namespace bs

@@ -46,6 +46,25 @@ __global__ void row_popcount_kernel(const uint32_t* __restrict__ X, int64_t n, i
   if (lane == 0) pop[row] = (int32_t)c;
 }
 
+// out[i] = |A[ia[i]] AND B[ib[i]]| for listed pairs (one thread per pair).
+__global__ void pair_list_kernel(const uint64_t* __restrict__ A, int64_t nA, const int32_t* __restrict__ ia,
+                                 const uint64_t* __restrict__ B, int64_t nB, const int32_t* __restrict__ ib,
+                                 int64_t n, int32_t W64, int32_t* __restrict__ out, int32_t* __restrict__ err) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t p = ia[i], q = ib[i];
+  if (p < 0 || p >= nA || q < 0 || q >= nB) {  // out-of-range row: reported, output 0
+    out[i] = 0;
+    if (err) atomicOr(err, 1);
+    return;
+  }
+  const uint64_t* a = A + (size_t)p * W64;
+  const uint64_t* b = B + (size_t)q * W64;
+  uint32_t c = 0;
+  for (int w = 0; w < W64; ++w) c += (uint32_t)__builtin_popcountll(a[w] & b[w]);
+  out[i] = (int32_t)c;
+}
+
 void launch_lut(int32_t N, double* t64, float* t32, hipStream_t s) {
   const int threads = 256;
   hipLaunchKernelGGL(build_lut_kernel, dim3((N + 1 + threads - 1) / threads), dim3(threads), 0, s, N,
@@ -256,4 +275,20 @@ extern "C" bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t
   a.nB = nB;
   a.W32 = N / 32;
   return launch_dense<true>(a, s);
+}
+
+extern "C" bs_status bs_pair_popcount(const uint64_t* A, int64_t nA, const int32_t* ia, const uint64_t* B,
+                                      int64_t nB, const int32_t* ib, int64_t n_pairs, int32_t N, int32_t* out,
+                                      int32_t* err_flag, void* stream) {
+  using namespace bs;
+  if (nA < 0 || nB < 0 || n_pairs < 0 || !valid_width(N)) return BS_ERR_ARG;
+  if (n_pairs > 0 && (!A || !B || !ia || !ib || !out)) return BS_ERR_NULL;
+  bs_status st = check_device();
+  if (st != BS_OK) return st;
+  if (n_pairs == 0) return BS_OK;
+  const int64_t blocks = (n_pairs + 255) / 256;
+  if (blocks > INT32_MAX) return BS_ERR_ARG;
+  hipLaunchKernelGGL(pair_list_kernel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), A, nA, ia, B, nB,
+                     ib, n_pairs, N / 64, out, err_flag);
+  return launch_status();
 }

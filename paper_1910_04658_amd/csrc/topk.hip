@@ -101,21 +101,6 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   return p;
 }
 
-template <int M>
-__device__ __forceinline__ float score_f32(float Ta, float Tb, float Tu) {
-  const float s = Ta + Tb;
-  const float ip = s - Tu;
-  if (M == BS_IP) return ip;
-  const float ham = s - (ip + ip);
-  if (M == BS_HAMMING) return ham;
-  if (M == BS_JACCARD) {
-    const float den = ip + ham;
-    return den == 0.0f ? 0.0f : ip / den;
-  }
-  const float pr = Ta * Tb;
-  return pr == 0.0f ? 0.0f : ip / sqrtf(pr);
-}
-
 // Larger key = better rank. Hamming ranks ascending, so its key is inverted.
 template <int M>
 __device__ __forceinline__ uint32_t score_key(float s) {
