@@ -234,6 +234,47 @@ def jaccard_mse(step, corpus, queries):
             "top100_pairs": mse_top, "top100_mean_estimate": mean_js_top}
 
 
+def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256, steps=600, batch=65536):
+    """Learned estimator vs closed form: train on ~10M near-duplicate pairs of
+    the benchmark distribution sketched at N = 256, test on ~1M held-out pairs."""
+    import torch
+
+    import datagen
+    from paper_1910_04658_amd import binding as bs
+    from paper_1910_04658_amd import learned
+    t = time.time()
+    tr = datagen.variant_groups(n_train_groups, group, seed=5005)
+    te = datagen.variant_groups(n_test_groups, group, seed=6006)
+    pi = datagen.random_map(tr.csr.d, N, datagen.SEED_PI + 7)
+    t_gen = time.time() - t
+    dtr = learned.sketch_pairs(tr, pi, N, dev)
+    dte = learned.sketch_pairs(te, pi, N, dev)
+    del tr, te
+    model = learned.Model(learned.init_master(0, dev))
+    torch.cuda.synchronize()
+    t = time.time()
+    model.train(dtr, steps=steps, batch=batch, lr=3e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.time() - t
+    pred = model.predict(dte)
+    base = learned.closed_form(dte)
+    out = {"N": N, "train_pairs": len(dtr), "heldout_pairs": len(dte), "steps": steps, "batch": batch,
+           "mse_learned": learned.mse(pred, dte), "mse_closed_form": learned.mse(base, dte),
+           "train_seconds": t_train, "data_seconds": t_gen}
+    # inference throughput on the held-out pairs
+    ws = bs.mlp_workspace(len(dte), N, dev)
+    o = torch.empty(len(dte), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        bs.mlp_forward(model.w, dte.xa, dte.xb, dte.xab, N, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        bs.mlp_forward(model.w, dte.xa, dte.xb, dte.xab, N, out=o, workspace=ws)
+    torch.cuda.synchronize()
+    out["infer_pairs_per_s"] = 20 * len(dte) / (time.perf_counter() - t)
+    return out
+
+
 def cpu_baseline(corpus, queries, pi, N, k, nq):
     """The CPU oracle (plain C, OpenMP over rows) on a bounded sample."""
     import numpy as np
@@ -269,6 +310,7 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=256, help="queries in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-estimator evaluation")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
@@ -373,6 +415,10 @@ def main():
                                  "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
     if not args.no_mse:
         out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.no_learned:
+        log("training the learned estimator ...")
+        out["learned_estimator"] = learned_eval(dev)
+        log("learned estimator: %s" % out["learned_estimator"])
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(corpus, queries, pis[args.N], args.N, k, args.cpu_queries)
