@@ -379,3 +379,53 @@ def variant_groups(n_groups: int, group_size: int, d: int = 100_000, mean: float
     union = la + lb - inter
     jac = np.where(union > 0, inter / np.maximum(union, 1), 0.0)
     return PairSet(csr, ia, ib, inter, jac)
+
+
+# ---------------------------------------------------------------------------
+# Large corpora generated on the device, chunk by chunk (serving workload)
+# ---------------------------------------------------------------------------
+
+def device_corpus_chunks(n: int, d: int, mean: float, sd: float, seed: int, device, chunk_rows: int = 1 << 18,
+                         s: float = 1.1, lo: int = 1, hi: int | None = None):
+    """Yields (indptr int32[m+1], indices int32[nnz]) device tensors for
+    consecutive chunks of an n-row corpus: lengths round(lognormal(mean, sd))
+    clipped to [lo, hi], ids drawn by Zipf(s) popularity *with* replacement
+    (a row may repeat an id; the binary vector is the set of its ids), ranks
+    mapped to ids by a seeded permutation. Uses torch's device generator only
+    to draw random numbers; nothing of the method is computed here."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    cdf = torch.cumsum(torch.arange(1, d + 1, device=device, dtype=torch.float64) ** -s, 0)
+    cdf /= cdf[-1].clone()
+    perm = torch.randperm(d, generator=g, device=device)
+    sigma2 = math.log1p((sd / mean) ** 2)
+    mu = math.log(mean) - sigma2 / 2
+    hi = hi if hi is not None else d
+    for r0 in range(0, n, chunk_rows):
+        m = min(chunk_rows, n - r0)
+        z = torch.randn(m, generator=g, device=device, dtype=torch.float64)
+        lens = torch.exp(mu + math.sqrt(sigma2) * z).round().clamp(lo, hi).to(torch.int64)
+        indptr = torch.zeros(m + 1, dtype=torch.int64, device=device)
+        torch.cumsum(lens, 0, out=indptr[1:])
+        nnz = int(indptr[-1].item())
+        if nnz >= 2 ** 31:
+            raise ValueError("chunk too large for an int32 CSR batch; lower chunk_rows")
+        u = torch.rand(nnz, generator=g, device=device, dtype=torch.float64)
+        ranks = torch.searchsorted(cdf, u).clamp_max(d - 1)
+        yield indptr.to(torch.int32), perm[ranks].to(torch.int32)
+
+
+def loguniform_lengths(rng: np.random.Generator, n: int, lo: int, hi: int) -> np.ndarray:
+    """Integer lengths with log-uniform distribution on [lo, hi]."""
+    return np.exp(rng.uniform(math.log(lo), math.log(hi + 1), n)).astype(np.int64).clip(lo, hi)
+
+
+def serving_queries(n: int, d: int, seed: int, lo: int = 10, hi: int = 5000, rate: float = 2000.0):
+    """n query vectors (log-uniform lengths in [lo, hi], Zipf(1.1) ids without
+    replacement) and Poisson arrival times (seconds) at `rate` queries/s."""
+    rng = np.random.default_rng(seed)
+    lens = loguniform_lengths(rng, n, lo, hi)
+    q = zipf_rows_fast(rng, lens, d, 1.1)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
+    return q, arrivals

@@ -37,7 +37,8 @@ void launch_row_popcount(const uint64_t* X, int64_t n, int32_t N, int32_t* pop, 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSampleMax = 4096;     // rows scored in the sample pass
+constexpr int kSampleMin = 4096;     // rows scored in the sample pass
+constexpr int kSampleMax = 15360;  // keys fit 60 KB of LDS in the sample select
 constexpr int kSelectLdsKeys = 4096; // candidate keys selected in LDS (else in place)
 constexpr int kStage = 128;          // per-wave staging entries in the scan pass
 constexpr int kFallbackBlocks = 16;
@@ -61,7 +62,11 @@ struct Plan {
 
 Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   Plan p;
-  p.S = nC < kSampleMax ? nC : kSampleMax;
+  // sample size: 4,096 rows, growing as nC/256 up to 15,360 for large corpora
+  // (the candidate count per query is about k * nC / S)
+  int64_t S = nC / 256;
+  S = S < kSampleMin ? kSampleMin : (S > kSampleMax ? kSampleMax : S);
+  p.S = nC < S ? nC : S;
   p.stride = p.S > 0 ? nC / p.S : 1;
   if (p.S == nC) {
     p.cap = nC;
@@ -73,7 +78,10 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
     if (cap > nC) cap = nC;
     p.cap = cap;
   }
-  p.F = nQ < kFallbackBlocks ? nQ : kFallbackBlocks;
+  // fallback blocks: at most 16, and at most 256 MB of whole-corpus key scratch
+  int64_t F = (INT64_C(256) << 20) / (8 * nC);
+  F = F < 1 ? 1 : (F > kFallbackBlocks ? kFallbackBlocks : F);
+  p.F = nQ < F ? nQ : F;
   size_t o = 0;
   p.off_t32 = o;
   o += align256((size_t)(N + 1) * 4);
