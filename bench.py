@@ -275,6 +275,48 @@ def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256,
     return out
 
 
+def serving_eval(dev, n_corpus=10_000_000, d=1_000_000, N=2048, k=50, n_req=4000, rate=2000.0,
+                 n_slots=3, max_batch=64):
+    """Continuous-batching server over a device-resident corpus of n_corpus
+    vectors (d = 10^6, lognormal lengths mean 400 sd 300, Zipf(1.1) ids),
+    sketched at N = 2048; queries of 10-5,000 set bits arrive as a Poisson
+    process at `rate` per second and get a top-50 cosine ranking."""
+    import torch
+
+    import datagen
+    from paper_1910_04658_amd import binding as bs
+    from paper_1910_04658_amd.serving import GpuExecutor, Server, make_requests
+    t = time.time()
+    pi = datagen.random_map(d, N, datagen.SEED_PI + 11)
+    pi_d = torch.from_numpy(pi).to(dev)
+    C = torch.empty((n_corpus, N // 64), dtype=torch.int64, device=dev)
+    popC = torch.empty(n_corpus, dtype=torch.int32, device=dev)
+    ws = bs._workspace(bs.sketch_workspace_size(d, N), dev)
+    r0 = 0
+    nnz = 0
+    for indptr, indices in datagen.device_corpus_chunks(n_corpus, d, 400.0, 300.0, seed=7007, device=dev,
+                                                         chunk_rows=1 << 18, hi=5000):
+        m = indptr.numel() - 1
+        bs.sketch(indptr, indices, pi_d, N, out=C[r0:r0 + m], popcounts=popC[r0:r0 + m], workspace=ws)
+        r0 += m
+        nnz += indices.numel()
+    torch.cuda.synchronize()
+    t_build = time.time() - t
+    q, arr = datagen.serving_queries(n_req, d, seed=8008, lo=10, hi=5000, rate=rate)
+    ex = GpuExecutor(C, popC, pi_d, N, k, "cosine", max_batch=max_batch, n_slots=n_slots,
+                     max_nnz=max_batch * 5000)
+    budget = 16 << 30
+    srv = Server(ex, n_slots=n_slots, max_batch=max_batch, mem_budget=budget)
+    srv.run(make_requests(q, arr)[:200], realtime=False)  # warm-up
+    online = srv.run(make_requests(q, arr), realtime=True)
+    offline = srv.run(make_requests(q, arr), realtime=False)
+    return {"corpus_rows": n_corpus, "corpus_nnz": nnz, "d": d, "N": N, "k": k, "measure": "cosine",
+            "corpus_sketch_GB": C.numel() * 8 / 1e9, "corpus_build_s": t_build,
+            "arrival_rate_qps": rate, "requests": n_req, "slots": n_slots, "max_batch": max_batch,
+            "mem_budget_GB": budget / 2 ** 30,
+            "online": online, "offline_all_at_once": offline}
+
+
 def cpu_baseline(corpus, queries, pi, N, k, nq):
     """The CPU oracle (plain C, OpenMP over rows) on a bounded sample."""
     import numpy as np
@@ -311,6 +353,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-estimator evaluation")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
@@ -415,6 +458,10 @@ def main():
                                  "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
     if not args.no_mse:
         out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.no_serving:
+        log("serving run ...")
+        out["serving"] = serving_eval(dev)
+        log("serving: %s" % out["serving"])
     if not args.no_learned:
         log("training the learned estimator ...")
         out["learned_estimator"] = learned_eval(dev)

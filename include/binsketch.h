@@ -232,12 +232,14 @@ void bs_timing_reset(void);
 int bs_timing_get(const char* name, double* total_ms, int64_t* count);
 
 /*
- * Testing hook, not for production callers: caps the per-query candidate
- * list of bs_topk at `cap` entries (0 restores the automatic size) so that
- * tests can drive the overflow path, which must return the same result.
- * Process-wide; not thread-safe. Always returns 0.
+ * Testing hook, not for production callers: caps the candidate slots that
+ * bs_topk keeps per (query, corpus slab) at `cap` (0 sends every query with a
+ * candidate outside the sample to the whole-corpus fallback; a negative value
+ * restores the automatic size) so that tests can drive the overflow path,
+ * which must return the same result. Process-wide; not thread-safe. Always
+ * returns 0.
  */
-int bs_debug_set_topk_capacity(int64_t cap);
+int bs_debug_set_topk_slab_capacity(int64_t cap);
 
 #ifdef __cplusplus
 }

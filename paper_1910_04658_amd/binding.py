@@ -84,8 +84,8 @@ def load():
             L.bs_mlp_train_step.restype = ctypes.c_int
             L.bs_mlp_to_bf16.argtypes = [p, p, p]
             L.bs_mlp_to_bf16.restype = ctypes.c_int
-            L.bs_debug_set_topk_capacity.argtypes = [i64]
-            L.bs_debug_set_topk_capacity.restype = ctypes.c_int
+            L.bs_debug_set_topk_slab_capacity.argtypes = [i64]
+            L.bs_debug_set_topk_slab_capacity.restype = ctypes.c_int
             _lib = L
     return _lib
 
@@ -268,8 +268,8 @@ def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool
     return out_idx, out_score
 
 
-def debug_set_topk_capacity(cap: int):
-    load().bs_debug_set_topk_capacity(int(cap))
+def debug_set_topk_slab_capacity(cap: int):
+    load().bs_debug_set_topk_slab_capacity(int(cap))
 
 
 def timing_enable(on: bool = True):

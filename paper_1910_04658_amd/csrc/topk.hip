@@ -13,18 +13,20 @@
 //     the sample rows scoring >= tau to the query's candidate list, and store
 //     per-query constants for the filter below. The k-th best over the whole
 //     corpus is >= tau, so every true top-k row scores >= tau.
-//  2. scan: every other (query, corpus row) pair. Lanes hold corpus rows in
-//     VGPRs, query words arrive on the scalar unit. Instead of evaluating the
-//     score (an IEEE division per pair) the kernel tests a conservative bound
-//     on T(x_u) that every pair scoring >= tau satisfies; survivors (a few
-//     percent) are staged per wave in LDS and appended 64 at a time with one
-//     vector atomic per lane.
-//  3. select: per query, exact scores of the candidates as unique 64-bit keys
-//     (score key, then inverted index), an exact radix select of the k-th key
-//     and a bitonic sort of the k winners.
-//  4. fallback: a query whose candidate list overflowed its capacity (e.g.
-//     massive exact ties) is recomputed over the whole corpus by a few blocks
-//     and selected the same way. Results never depend on which path ran.
+//  2. scan: every other (query, corpus row) pair. Lanes hold queries (words in
+//     VGPRs), corpus rows arrive on the scalar unit. Instead of evaluating the
+//     score (an IEEE division per pair) the kernel tests x_ab >= m[x_c][q], a
+//     per-query integer bound that every pair scoring >= tau satisfies. Each
+//     lane writes its survivors (a few percent) into the query's own slot
+//     range for that corpus slab, counted in a register: no atomics.
+//  3. select: per query, the sample and slab candidates are compacted (block
+//     scan over slab counts), scored exactly as unique 64-bit keys (score
+//     key, then inverted index), the k-th key found by radix select and the
+//     k winners sorted (bitonic).
+//  4. fallback: a query with more survivors in one slab than its slot range
+//     holds (e.g. massive exact ties) is recomputed over the whole corpus by a
+//     few blocks and selected the same way. Results never depend on which path
+//     ran.
 #include <float.h>
 
 #include "bs_common.h"
@@ -39,12 +41,12 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kSampleMin = 4096;     // rows scored in the sample pass
 constexpr int kSampleMax = 15360;  // keys fit 60 KB of LDS in the sample select
-constexpr int kSelectLdsKeys = 4096; // candidate keys selected in LDS (else in place)
-constexpr int kStage = 128;          // per-wave staging entries in the scan pass
+constexpr int kSelectLdsKeys = 6144; // candidate keys selected in LDS (else in a global buffer)
+constexpr int kSelChunk = 1024;      // slabs compacted per step of the select kernel
+constexpr int kScanWaves = 16384;    // waves of the scan grid, about
+constexpr int kRowWaves = 4096;      // waves of the row-lane scan (small batches)
+constexpr int kRowsMaxQ = 64;        // largest batch of the row-lane scan
 constexpr int kFallbackBlocks = 16;
-// Candidate counters sit one per 256-byte line: every corpus slab bumps every
-// query's counter, and atomics that share a line serialise.
-constexpr int kCntStride = 64;
 
 struct QConst {  // per-query constants written by the sample pass
   float tau;     // k-th best sample score
@@ -55,9 +57,11 @@ struct QConst {  // per-query constants written by the sample pass
 };
 
 struct Plan {
-  int64_t S, stride, cap, F;
-  size_t off_t32, off_popq, off_popc, off_qc, off_cnt, off_cand, off_scratch, off_mtab, off_ovf, off_skeys,
-      off_sxab, total;
+  int64_t S, stride, F;
+  int64_t qpl, ngrp, nqb4, n_slabs, slab, scap, kmax;  // scan geometry
+  bool rows;                                          // row-lane scan (small batches)
+  size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_slots, off_qovf, off_keys,
+      off_scratch, off_mtab, off_ovf, off_skeys, total;
 };
 
 Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
@@ -68,43 +72,65 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   S = S < kSampleMin ? kSampleMin : (S > kSampleMax ? kSampleMax : S);
   p.S = nC < S ? nC : S;
   p.stride = p.S > 0 ? nC / p.S : 1;
-  if (p.S == nC) {
-    p.cap = nC;
+  // scan geometry: waves of QPL x 64 queries, four per block, ~16k waves
+  const int W32 = N / 32;
+  const bool pow2 = (W32 & (W32 - 1)) == 0;
+  p.qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && W32 == 16) ? 2 : 1);
+  const int64_t nqb = (nQ + 63) / 64;
+  p.ngrp = (nqb + p.qpl - 1) / p.qpl;
+  p.nqb4 = (p.ngrp + 3) / 4;
+  // A batch of at most 64 queries leaves most lanes of a query-lane wave
+  // idle and streams the corpus through the scalar unit: it is scanned with
+  // corpus rows on the lanes instead, each wave over a run of 64-row tiles.
+  p.rows = nQ <= kRowsMaxQ && pow2 && W32 <= 128;
+  if (p.rows) {
+    const int64_t tiles = (nC + kWave - 1) / kWave;
+    const int64_t tpw = (tiles + kRowWaves - 1) / kRowWaves;
+    p.slab = tpw * kWave;
   } else {
-    const int64_t per = (nC + p.S - 1) / p.S;
-    int64_t cap = 4 * (int64_t)k * per;
-    cap = (cap + 255) / 256 * 256;
-    if (cap < p.S) cap = p.S;
-    if (cap > nC) cap = nC;
-    p.cap = cap;
+    int64_t n_slabs = p.ngrp > 0 ? (kScanWaves + p.ngrp - 1) / p.ngrp : 1;
+    if (n_slabs > nC) n_slabs = nC;
+    if (n_slabs < 1) n_slabs = 1;
+    p.slab = (nC + n_slabs - 1) / n_slabs;
   }
+  p.n_slabs = (nC + p.slab - 1) / p.slab;
+  // candidate slots per (query, slab): the expected count e = slab * k / S
+  // (the threshold is the k-th best of S sampled rows) plus six standard
+  // deviations and a margin for ties at the threshold, so that overflow into
+  // the fallback path is rare
+  const double e = p.S > 0 ? (double)p.slab * k / (double)p.S : 0.0;
+  int64_t scap = (int64_t)ceil(2.0 * e + 6.0 * sqrt(e)) + 8;
+  p.scap = scap < p.slab ? scap : p.slab;
+  if (p.S >= nC) {  // the sample covers the corpus: no scan, no slabs
+    p.n_slabs = 0;
+    p.scap = 0;
+  }
+  p.kmax = p.S + p.n_slabs * p.scap;
   // fallback blocks: at most 16, and at most 256 MB of whole-corpus key scratch
   int64_t F = (INT64_C(256) << 20) / (8 * nC);
   F = F < 1 ? 1 : (F > kFallbackBlocks ? kFallbackBlocks : F);
   p.F = nQ < F ? nQ : F;
+  const size_t nQs = (size_t)nQ;
   size_t o = 0;
-  p.off_t32 = o;
-  o += align256((size_t)(N + 1) * 4);
-  p.off_popq = o;
-  o += align256((size_t)nQ * 4);
-  p.off_popc = o;
-  o += align256((size_t)nC * 4);
-  p.off_qc = o;
-  o += align256((size_t)nQ * sizeof(QConst));
-  p.off_cnt = o;
-  o += align256((size_t)nQ * 4 * kCntStride);
-  p.off_cand = o;
-  o += align256((size_t)nQ * (size_t)p.cap * 8);
-  p.off_scratch = o;
-  o += align256((size_t)p.F * (size_t)nC * 8);
-  p.off_mtab = o;
-  o += align256((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
-  p.off_ovf = o;
-  o += align256((size_t)(nQ + 1) * 4);
-  p.off_skeys = o;
-  o += align256((size_t)nQ * (size_t)p.S * 4);
-  p.off_sxab = o;
-  o += align256((size_t)nQ * (size_t)p.S * 4);
+  auto take = [&o](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  p.off_t32 = take((size_t)(N + 1) * 4);
+  p.off_popq = take(nQs * 4);
+  p.off_popc = take((size_t)nC * 4);
+  p.off_qc = take(nQs * sizeof(QConst));
+  p.off_cnts = take(nQs * 4);
+  p.off_cands = take(nQs * (size_t)p.S * 8);
+  p.off_scnt = take(nQs * (size_t)p.n_slabs * 4);
+  p.off_slots = take(nQs * (size_t)p.n_slabs * (size_t)p.scap * 8);
+  p.off_qovf = take(nQs * 4);
+  p.off_keys = take(nQs * (size_t)p.kmax * 8);
+  p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
+  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
+  p.off_ovf = take((nQs + 1) * 4);
+  p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
   return p;
 }
@@ -208,16 +234,19 @@ struct TopkArgs {
   const int32_t* __restrict__ popQ;
   const int32_t* __restrict__ popC;
   QConst* __restrict__ qc;
-  int32_t* __restrict__ cnt;       // [nQ][kCntStride], entry 0 used
-  uint64_t* __restrict__ cand;     // [nQ][cap]
+  int32_t* __restrict__ cnts;      // [nQ] sample candidates per query
+  uint64_t* __restrict__ cands;    // [nQ][S] sample candidates (x_ab << 32 | row)
+  int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
+  uint64_t* __restrict__ slots;    // [nQ][n_slabs][scap] scan candidates
+  int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
+  uint64_t* __restrict__ keys;     // [nQ][kmax] compacted keys (large candidate sets)
   uint64_t* __restrict__ scratch;  // [F][nC]
   uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
   int32_t* __restrict__ ovf;       // [1 + nQ]: count, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
-  int32_t* __restrict__ sxab;      // [nQ][S] sample pair counts
   int32_t* __restrict__ out_idx;   // [nQ][k]
   float* __restrict__ out_score;   // [nQ][k] or null
-  int64_t nQ, nQp, nC, S, stride, cap;
+  int64_t nQ, nQp, nC, S, stride, n_slabs, slab, nqb4, scap, kmax;
   int32_t N, W32, k, kpad;
 };
 
@@ -314,7 +343,6 @@ __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a
     const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc]);
     if (i_ok) {
       a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
-      a.sxab[(size_t)q * a.S + i] = (int32_t)acc;
     }
   }
 }
@@ -336,18 +364,18 @@ __global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(TopkArgs a
   if (q == 0 && threadIdx.x == 0) a.ovf[0] = 0;
   __syncthreads();
   const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed);
-  uint64_t* cq = a.cand + (size_t)q * a.cap;
-  const int32_t* xab = a.sxab + (size_t)q * a.S;
+  uint64_t* cq = a.cands + (size_t)q * a.S;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     if (keys[i] >= tau_key) {
       const uint32_t slot = atomicAdd(&nsel, 1u);
-      cq[slot] = ((uint64_t)(uint32_t)xab[i] << 32) | (uint32_t)(i * a.stride);
+      cq[slot] = ((uint64_t)keys[i] << 32) | (uint32_t)~(uint32_t)(i * a.stride);
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     const int32_t xq = a.popQ[q];
-    a.cnt[q * kCntStride] = (int32_t)nsel;
+    a.cnts[q] = (int32_t)nsel;
+    a.qovf[q] = 0;
     a.qc[q] = make_qconst<M>(key_score<M>(tau_key), a.t32[xq], xq);
   }
 }
@@ -398,47 +426,6 @@ __global__ __launch_bounds__(kThreads) void topk_bound_kernel(TopkArgs a) {
 }
 
 // ---- pass 2b: filtered scan ----------------------------------------------------
-struct Staged {
-  int32_t q, row, xab;
-};
-
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Append the first `n` (<= 64) staged entries: one vector atomic per lane.
-__device__ __forceinline__ void flush_stage(Staged* st, int n, int lane, const TopkArgs& a) {
-  if (lane < n) {
-    const Staged e = st[lane];
-    const int32_t slot = atomicAdd(a.cnt + (size_t)e.q * kCntStride, 1);
-    if (slot < a.cap) a.cand[(size_t)e.q * a.cap + slot] = ((uint64_t)(uint32_t)e.xab << 32) | (uint32_t)e.row;
-  }
-}
-
-// Stage the lanes of `take` (a wave-uniform ballot) and flush full batches.
-__device__ __forceinline__ void stage_take(bool take, int32_t q, int32_t row, int32_t xab, Staged* stage,
-                                           int& fill, int lane, const TopkArgs& a) {
-  const uint64_t mask = __builtin_amdgcn_ballot_w64(take);
-  if (!mask) return;
-  const int pos = fill + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-  if (take) stage[pos] = Staged{q, row, xab};
-  fill += __builtin_popcountll(mask);
-  if (fill >= kWave) {
-    wave_sync_lds();
-    flush_stage(stage, kWave, lane, a);
-    wave_sync_lds();
-    Staged rest = {0, 0, 0};
-    if (lane < fill - kWave) rest = stage[kWave + lane];
-    wave_sync_lds();
-    if (lane < fill - kWave) stage[lane] = rest;
-    fill -= kWave;
-    wave_sync_lds();
-  }
-}
-
 // One wave = QPL groups of 64 queries (one query per lane per group, words in
 // VGPRs) x a slab of corpus rows streamed through the scalar unit in pieces
 // of PS words, each piece fetched one step ahead of its use. The four waves
@@ -449,12 +436,10 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
                                                              int64_t nqb4) {
   constexpr int PS = W32T < 32 ? W32T : 32;  // words per scalar piece
   constexpr int P = W32T / PS;               // pieces per row
-  __shared__ Staged stage_all[kThreads / kWave][kStage];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t bid = blockIdx.x;
   const int64_t sl = bid / nqb4;
   const int64_t qg0 = ((bid % nqb4) * (kThreads / kWave) + wid) * QPL;  // first 64-query group
-  Staged* stage = stage_all[wid];
   const int64_t c_begin = sl * slab;
   const int64_t c_end = c_begin + slab < a.nC ? c_begin + slab : a.nC;
   if (qg0 * kWave >= a.nQ || c_begin >= c_end) return;  // wave-uniform
@@ -478,7 +463,13 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
 #pragma unroll
   for (int j = 0; j < QPL; ++j) moff[j] = (qg0 + j < ngroups ? qg0 + j : qg0) * kWave + lane;
   const uint16_t* mt = a.mtab;
-  int fill = 0;
+  int cnt[QPL];
+  uint64_t* dst[QPL];  // this (query, slab)'s slot range
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) {
+    cnt[j] = 0;
+    dst[j] = a.slots + ((size_t)(q_ok[j] ? q[j] : 0) * a.n_slabs + sl) * a.scap;
+  }
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row
   const int64_t s_end = a.S * a.stride;
 
@@ -529,13 +520,21 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
 #pragma unroll
     for (int j = 0; j < QPL; ++j) {
       const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
-      stage_take(take, (int32_t)q[j], (int32_t)c, (int32_t)acc[j], stage, fill, lane, a);
+      if (take) {
+        if (cnt[j] < a.scap) dst[j][cnt[j]] = ((uint64_t)acc[j] << 32) | (uint32_t)c;
+        ++cnt[j];
+      }
       m[j] = mn[j];
     }
     x2 = x3;
   }
-  wave_sync_lds();
-  flush_stage(stage, fill, lane, a);
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) {
+    if (q_ok[j]) {
+      a.scnt[(size_t)q[j] * a.n_slabs + sl] = cnt[j] < a.scap ? cnt[j] : (int32_t)a.scap;
+      if (cnt[j] > a.scap) a.qovf[q[j]] = 1;
+    }
+  }
 }
 
 // Generic widths (N not a power of two, or N > 4096): query words re-read per
@@ -543,13 +542,11 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
 template <int WC>
 __global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a, int64_t n_slabs, int64_t slab,
                                                                      int64_t nqb4) {
-  __shared__ Staged stage_all[kThreads / kWave][kStage];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   const int64_t bid = blockIdx.x;
   const int64_t sl = bid / nqb4;
   const int64_t qb = (bid % nqb4) * (kThreads / kWave) + wid;
   const int64_t q = qb * kWave + lane;
-  Staged* stage = stage_all[wid];
   const int64_t c_begin = sl * slab;
   const int64_t c_end = c_begin + slab < a.nC ? c_begin + slab : a.nC;
   if (qb * kWave >= a.nQ || c_begin >= c_end) return;
@@ -559,7 +556,8 @@ __global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a,
   const uint32_t* qrow = reinterpret_cast<const uint32_t*>(a.Q) + (size_t)(q_ok ? q : a.nQ - 1) * W32;
   const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C);
   const uint16_t* mt = a.mtab + q;
-  int fill = 0;
+  int cnt = 0;
+  uint64_t* dst = a.slots + ((size_t)(q_ok ? q : 0) * a.n_slabs + sl) * a.scap;
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;
   const int64_t s_end = a.S * a.stride;
   for (int64_t c = c_begin; c < c_end; ++c) {
@@ -577,17 +575,113 @@ __global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a,
     const bool in_sample = c == next_s && c < s_end;
     if (c == next_s) next_s += a.stride;
     const bool take = q_ok && !in_sample && acc >= (uint32_t)m;
-    stage_take(take, (int32_t)q, (int32_t)c, (int32_t)acc, stage, fill, lane, a);
+    if (take) {
+      if (cnt < a.scap) dst[cnt] = ((uint64_t)acc << 32) | (uint32_t)c;
+      ++cnt;
+    }
   }
-  wave_sync_lds();
-  flush_stage(stage, fill, lane, a);
+  if (q_ok) {
+    a.scnt[(size_t)q * a.n_slabs + sl] = cnt < a.scap ? cnt : (int32_t)a.scap;
+    if (cnt > a.scap) a.qovf[q] = 1;
+  }
 }
 
-// ---- pass 3: exact selection of each query's candidates -----------------------
 template <int M>
 __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
   return ((uint64_t)score_key<M>(sc) << 32) | (uint64_t)(~idx);
 }
+
+// Row-lane scan for batches of at most 64 queries. Each wave owns one slab:
+// a run of 64-row tiles. Lane l holds row (tile + l) in VGPRs; the queries
+// arrive in turn on the scalar unit, so the corpus is read from HBM exactly
+// once with every lane busy. The filter is the predicate the threshold table
+// encodes, T(x_u) <= bound(q, x_c), evaluated directly with T in LDS. A
+// query's survivors in the slab are numbered by a wave prefix count (ballot);
+// lane j of the counter register holds query j's running count. Survivors
+// are stored as final selection keys (the score is at hand here).
+template <int M, int W32T>
+__global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(TopkArgs a) {
+  extern __shared__ float lut[];  // T[0..N]
+  for (int x = threadIdx.x; x <= a.N; x += kThreads) lut[x] = a.t32[x];
+  __syncthreads();
+  constexpr int PS = W32T < 32 ? W32T : 32;  // query words per scalar piece
+  const int lane = threadIdx.x % kWave;
+  const int64_t sl = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+  if (sl >= a.n_slabs) return;  // wave-uniform
+  const int64_t r_begin = sl * a.slab;
+  const int64_t r_end = r_begin + a.slab < a.nC ? r_begin + a.slab : a.nC;
+  const int nQ = (int)a.nQ;
+  const uint32_t stride = (uint32_t)a.stride;
+  const uint32_t S = (uint32_t)a.S;
+  const int32_t N = a.N;
+  const uint32_t* Q32 = reinterpret_cast<const uint32_t*>(a.Q);
+  const cptr<QConst> qc = as_const(a.qc);
+  const cptr<int32_t> popQ = as_const(a.popQ);
+  int cntv = 0;  // lane j: survivors of query j in this slab so far
+  for (int64_t r0 = r_begin; r0 < r_end; r0 += kWave) {
+    const int64_t r = r0 + lane;
+    const bool ok = r < r_end;
+    const int64_t rr = ok ? r : r_end - 1;
+    uint32_t row[W32T];
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(a.C) + (size_t)rr * W32T;
+      if (W32T >= 4) {
+#pragma unroll
+        for (int w = 0; w < W32T; w += 4) {
+          const uint4 v = *reinterpret_cast<const uint4*>(src + w);
+          row[w] = v.x;
+          row[w + 1] = v.y;
+          row[w + 2] = v.z;
+          row[w + 3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int w = 0; w < W32T; ++w) row[w] = src[w];
+      }
+    }
+    int32_t xc = a.popC[rr];
+    xc = xc < 0 ? 0 : (xc > N ? N : xc);
+    const float Tc = lut[xc];
+    const float sTc = M == BS_COSINE ? sqrtf(Tc) : 0.0f;
+    const uint32_t ur = (uint32_t)rr;
+    const uint32_t si = ur / stride;
+    const bool live = ok && !(ur == si * stride && si < S);  // sampled rows were ranked by the sample pass
+    for (int q = 0; q < nQ; ++q) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int p = 0; p < W32T / PS; ++p) {
+        const cptr<uint32_t> qw = as_const(Q32 + (size_t)q * W32T + p * PS);
+#pragma unroll
+        for (int w = 0; w < PS; ++w) acc += popc32(row[p * PS + w] & qw[w]);
+      }
+      float bound = fmaf(qc[q].Tq + Tc, qc[q].A, qc[q].C);
+      if (M == BS_COSINE) bound = fmaf(sTc, qc[q].B, bound);
+      int32_t xu = popQ[q] + xc - (int32_t)acc;
+      xu = xu < 0 ? 0 : (xu > N ? N : xu);
+      const float Tu = lut[xu];
+      const bool take = live && Tu <= bound;
+      const uint64_t bal = __ballot(take);
+      if (bal) {
+        const int base = __builtin_amdgcn_readlane(cntv, q);
+        if (take) {
+          const int slot = base + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+          if (slot < a.scap) {
+            const float sc = score_f32<M>(lut[popQ[q]], Tc, Tu);
+            a.slots[((size_t)q * a.n_slabs + sl) * a.scap + slot] = make_key<M>(sc, (uint32_t)rr);
+          }
+        }
+        if (lane == q) cntv += __popcll(bal);
+      }
+    }
+  }
+  if (lane < nQ) {
+    a.scnt[(size_t)lane * a.n_slabs + sl] = cntv < a.scap ? cntv : (int32_t)a.scap;
+    if (cntv > a.scap) a.qovf[lane] = 1;
+  }
+}
+
+// ---- pass 3: exact selection of each query's candidates -----------------------
 
 template <int M>
 __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a,
@@ -616,33 +710,83 @@ __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, con
 }
 
 template <int M>
+__device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, const TopkArgs& a) {
+  const uint32_t idx = (uint32_t)e;
+  const int32_t xab = (int32_t)(e >> 32);
+  const int32_t xc = a.popC[idx];
+  return make_key<M>(score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]), idx);
+}
+
+// Slot entries of the query-lane scan are (x_ab << 32 | row) and are scored
+// here (RAW); the row-lane scan and the sample pass store final keys.
+template <int M, bool RAW>
 __global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
   extern __shared__ uint64_t sm[];  // sel[kpad], then keys[kSelectLdsKeys]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
+  __shared__ uint32_t off[kSelChunk + 1];
   __shared__ uint64_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
+  __shared__ uint32_t total_s;
+  constexpr int PER = kSelChunk / kThreads;
   const int64_t q = blockIdx.x;
-  const int64_t n = a.cnt[q * kCntStride];
-  if (n > a.cap) {  // overflowed: hand the query to the fallback kernel
+  if (a.qovf[q]) {  // a slab overflowed its slots: hand the query to the fallback kernel
     if (threadIdx.x == 0) a.ovf[1 + atomicAdd(a.ovf, 1)] = (int32_t)q;
     return;
   }
+  const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
+  // 1. candidate count
+  uint32_t part = 0;
+  for (int64_t i = threadIdx.x; i < a.n_slabs; i += kThreads) part += (uint32_t)sc[i];
+  const uint32_t incl0 = block_incl_scan(part, wsum);
+  if (threadIdx.x == kThreads - 1) total_s = incl0;
+  __syncthreads();
+  const int64_t ns = a.cnts[q];
+  const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  uint64_t* cq = a.cand + (size_t)q * a.cap;
-  uint64_t* keys = n <= kSelectLdsKeys ? sm + a.kpad : cq;
+  uint64_t* keys = n <= kSelectLdsKeys ? sm + a.kpad : a.keys + (size_t)q * a.kmax;
   const int32_t xq = a.popQ[q];
   const float Tq = a.t32[xq];
-  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
-    const uint64_t e = cq[i];
-    const uint32_t idx = (uint32_t)e;
-    const int32_t xab = (int32_t)(e >> 32);
-    const int32_t xc = a.popC[idx];
-    const float sc = score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]);
-    keys[i] = make_key<M>(sc, idx);
+  // 2. compact: the sample's candidates, then every slab's slots in slab order.
+  // Per chunk of slabs, an exclusive scan of the counts goes to LDS and every
+  // thread takes output positions j, t + 256, ..., finding the slab of j by
+  // binary search, so that no thread walks a long slab alone.
+  const uint64_t* cs = a.cands + (size_t)q * a.S;
+  for (int64_t i = threadIdx.x; i < ns; i += kThreads) keys[i] = cs[i];
+  const uint64_t* slots = a.slots + (size_t)q * a.n_slabs * a.scap;
+  int64_t base = ns;
+  for (int64_t c0 = 0; c0 < a.n_slabs; c0 += kSelChunk) {
+    uint32_t cnt[PER], sum = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int64_t i = c0 + threadIdx.x * PER + u;
+      cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
+      sum += cnt[u];
+    }
+    const uint32_t incl = block_incl_scan(sum, wsum);
+    uint32_t o = incl - sum;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      off[threadIdx.x * PER + u] = o;
+      o += cnt[u];
+    }
+    if (threadIdx.x == kThreads - 1) off[kSelChunk] = incl;
+    __syncthreads();
+    const uint32_t T = off[kSelChunk];
+    for (uint32_t j = threadIdx.x; j < T; j += kThreads) {
+      int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= j) lo = mid;
+        else hi = mid - 1;
+      }
+      const uint64_t e = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
+      keys[base + j] = RAW ? cand_key<M>(e, xq, Tq, a) : e;
+    }
+    base += T;
+    __syncthreads();
   }
-  __syncthreads();
   select_and_write<M>(keys, n, q, a, sel, hist, wsum, &bprefix, &bneed, &nsel);
 }
 
@@ -715,7 +859,20 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
                        a);
   }
   // 2. thresholds, then scan the rest of the corpus
-  if (p.S < a.nC) {
+  if (p.S < a.nC && p.rows) {
+    ScopedTiming timing("topk_scan", s);
+    const dim3 g((unsigned)((p.n_slabs + kThreads / kWave - 1) / (kThreads / kWave))), b(kThreads);
+    const size_t lds = (size_t)(a.N + 1) * 4;
+    switch (a.W32) {
+      case 2: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 2>), g, b, lds, s, a); break;
+      case 4: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 4>), g, b, lds, s, a); break;
+      case 8: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 8>), g, b, lds, s, a); break;
+      case 16: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 16>), g, b, lds, s, a); break;
+      case 32: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 32>), g, b, lds, s, a); break;
+      case 64: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 64>), g, b, lds, s, a); break;
+      default: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 128>), g, b, lds, s, a); break;
+    }
+  } else if (p.S < a.nC) {
     {
       ScopedTiming timing("topk_bound", s);
       const dim3 g((unsigned)(a.nQp / kWave), (unsigned)((a.N + 1 + kBoundX - 1) / kBoundX));
@@ -726,14 +883,7 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
     }
     const int W32 = a.W32;
     const bool pow2 = (W32 & (W32 - 1)) == 0;
-    const int qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && W32 == 16) ? 2 : 1);  // queries per lane
-    const int64_t nqb = (a.nQ + kWave - 1) / kWave;                 // 64-query groups
-    const int64_t ngrp = (nqb + qpl - 1) / qpl;                     // waves per slab
-    const int64_t nqb4 = (ngrp + 3) / 4;                            // blocks per slab
-    int64_t n_slabs = (16384 + ngrp - 1) / ngrp;                    // ~16k waves in all
-    if (n_slabs > a.nC) n_slabs = a.nC;
-    const int64_t slab = (a.nC + n_slabs - 1) / n_slabs;
-    n_slabs = (a.nC + slab - 1) / slab;
+    const int64_t n_slabs = p.n_slabs, slab = p.slab, nqb4 = p.nqb4;
     const int64_t grid = n_slabs * nqb4;
     if (grid > INT32_MAX) return BS_ERR_ARG;
     ScopedTiming timing("topk_scan", s);
@@ -765,7 +915,10 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
   {
     const size_t lds = (size_t)a.kpad * 8 + (size_t)kSelectLdsKeys * 8;
     ScopedTiming timing("topk_select", s);
-    hipLaunchKernelGGL((topk_select_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
+    if (p.rows)
+      hipLaunchKernelGGL((topk_select_kernel<M, false>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
+    else
+      hipLaunchKernelGGL((topk_select_kernel<M, true>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
   }
   // 4. fallback for overflowed queries (exits at once when none overflowed)
   if (p.S < a.nC) {
@@ -778,8 +931,8 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
 
 }  // namespace
 
-// Capacity override for tests of the overflow path (0 = automatic).
-static int64_t g_cap_override = 0;
+// Slot-count override for tests of the overflow path (negative = automatic).
+static int64_t g_scap_override = -1;
 
 }  // namespace bs
 
@@ -789,8 +942,8 @@ extern "C" size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int3
   return make_plan(nQ, nC, N, k).total;
 }
 
-extern "C" int bs_debug_set_topk_capacity(int64_t cap) {
-  bs::g_cap_override = cap < 0 ? 0 : cap;
+extern "C" int bs_debug_set_topk_slab_capacity(int64_t cap) {
+  bs::g_scap_override = cap < 0 ? -1 : cap;
   return 0;
 }
 
@@ -810,7 +963,10 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   bs_status st = check_device();
   if (st != BS_OK) return st;
   if (nQ == 0) return BS_OK;
-  if (g_cap_override > 0 && g_cap_override >= p.S && g_cap_override < p.cap) p.cap = g_cap_override;
+  if (g_scap_override >= 0 && g_scap_override < p.scap) {  // fewer slots within the same layout size
+    p.scap = g_scap_override;
+    p.kmax = p.S + p.n_slabs * p.scap;
+  }
   char* ws = static_cast<char*>(workspace);
   TopkArgs a;
   a.Q = Q;
@@ -820,10 +976,13 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   a.popC = popC ? popC : reinterpret_cast<const int32_t*>(ws + p.off_popc);
   a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
   a.skeys = reinterpret_cast<uint32_t*>(ws + p.off_skeys);
-  a.sxab = reinterpret_cast<int32_t*>(ws + p.off_sxab);
   a.qc = reinterpret_cast<QConst*>(ws + p.off_qc);
-  a.cnt = reinterpret_cast<int32_t*>(ws + p.off_cnt);
-  a.cand = reinterpret_cast<uint64_t*>(ws + p.off_cand);
+  a.cnts = reinterpret_cast<int32_t*>(ws + p.off_cnts);
+  a.cands = reinterpret_cast<uint64_t*>(ws + p.off_cands);
+  a.scnt = reinterpret_cast<int32_t*>(ws + p.off_scnt);
+  a.slots = reinterpret_cast<uint64_t*>(ws + p.off_slots);
+  a.qovf = reinterpret_cast<int32_t*>(ws + p.off_qovf);
+  a.keys = reinterpret_cast<uint64_t*>(ws + p.off_keys);
   a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
   a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
   a.out_idx = out_idx;
@@ -833,7 +992,11 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   a.nC = nC;
   a.S = p.S;
   a.stride = p.stride;
-  a.cap = p.cap;
+  a.n_slabs = p.n_slabs;
+  a.slab = p.slab;
+  a.nqb4 = p.nqb4;
+  a.scap = p.scap;
+  a.kmax = p.kmax;
   a.N = N;
   a.W32 = N / 32;
   a.k = k;

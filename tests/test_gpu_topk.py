@@ -52,21 +52,39 @@ def test_scan_path(m, N, k, dev):
     assert_topk_equal(gi, gs, oi, osc)
 
 
+@pytest.mark.parametrize("m", MEASURES)
+@pytest.mark.parametrize("N,nq", [(256, 130), (320, 70), (1024, 65), (8192, 20)])
+def test_scan_path_query_lanes(m, N, nq, dev):
+    """Batches above 64 queries (and widths the row-lane scan does not take:
+    N = 320 is not a power-of-two word count, N = 8192 exceeds 128 words) go
+    through the query-lane scan; ragged query counts."""
+    c = _mid("c20011", lambda: datagen.lognormal_corpus(20011, d=30000, seed=22))
+    w, S = sketch_both(c, N, 6, dev)
+    q = np.linspace(0, 20010, nq).astype(np.int64)
+    gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, N, m, 40)
+    sel = np.arange(0, nq, max(1, nq // 12))
+    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, N, m, 40)
+    assert_topk_equal(gi[sel], gs[sel], oi, osc)
+
+
 @pytest.mark.parametrize("m", [oracle.JS, oracle.HAM])
-def test_overflow_fallback_path(m, dev):
-    """A candidate capacity of exactly the sample size forces every query onto
-    the whole-corpus fallback; the result must not change."""
+@pytest.mark.parametrize("nq", [20, 80])
+def test_overflow_fallback_path(m, nq, dev):
+    """No candidate slots outside the sample sends every query with a scan
+    survivor to the whole-corpus fallback, and one slot sends some; the result
+    must not change."""
     from paper_1910_04658_amd import binding as bs
     c = datagen.lognormal_corpus(9000, d=20000, seed=23)
     w, S = sketch_both(c, 512, 7, dev)
-    q = np.arange(0, 9000, 450)
-    try:
-        bs.debug_set_topk_capacity(4096)
-        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 512, m, 50)
-    finally:
-        bs.debug_set_topk_capacity(0)
+    q = np.linspace(0, 8999, nq).astype(np.int64)
     oi, osc = oracle.topk(sets_rows(S, q), S, 512, m, 50)
-    assert_topk_equal(gi, gs, oi, osc)
+    for cap in (0, 1):
+        try:
+            bs.debug_set_topk_slab_capacity(cap)
+            gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 512, m, 50)
+        finally:
+            bs.debug_set_topk_slab_capacity(-1)
+        assert_topk_equal(gi, gs, oi, osc)
 
 
 def test_exact_ties_break_by_index(dev):
@@ -117,6 +135,11 @@ def test_full_size_query_vs_corpus(N, dev):
     i = idx.cpu().numpy()
     assert (np.diff(s, axis=1) <= 0).all()
     assert all(len(set(r)) == 100 for r in i) and i.min() >= 0 and i.max() < 100_000
+
+
+def _mid(key, fn):
+    from conftest import shared_input
+    return shared_input(key, fn)
 
 
 def _big(key, fn):
