@@ -429,3 +429,61 @@ def serving_queries(n: int, d: int, seed: int, lo: int = 10, hi: int = 5000, rat
     q = zipf_rows_fast(rng, lens, d, 1.1)
     arrivals = np.cumsum(rng.exponential(1.0 / rate, n)) if rate > 0 else np.zeros(n)
     return q, arrivals
+
+
+# ---- batches of uneven problems -------------------------------------------------
+SEED_BATCH = 4004
+BATCH_WIDTHS = (128, 512, 2048, 8192)
+
+
+@dataclasses.dataclass
+class BatchSpec:
+    n: int        # corpus rows
+    d: int        # dimension
+    mean: float   # mean set bits per row
+    N: int        # sketch width
+    nq: int       # query rows
+    seed: int
+
+
+def batch_specs(n_problems: int = 64, seed: int = SEED_BATCH, n_lo: int = 1000, n_hi: int = 200_000,
+                d_lo: int = 10_000, d_hi: int = 1_000_000, m_lo: float = 20.0, m_hi: float = 2000.0,
+                widths=BATCH_WIDTHS, q_frac: float = 0.01, q_min: int = 100) -> list:
+    """Shapes of a batch of independent problems: corpus size, dimension and
+    mean row weight each log-uniform (a power law with exponent -1) on their
+    ranges, the width uniform over `widths`, queries q_frac of the rows (at
+    least q_min)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_problems):
+        n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        d = int(round(math.exp(rng.uniform(math.log(d_lo), math.log(d_hi)))))
+        mean = float(math.exp(rng.uniform(math.log(m_lo), math.log(m_hi))))
+        N = int(widths[int(rng.integers(len(widths)))])
+        nq = max(q_min, int(round(q_frac * n)))
+        out.append(BatchSpec(n, d, mean, N, nq, seed * 1000 + i))
+    return out
+
+
+def device_batch(specs: list, device, k: int = 100, cv: float = 0.65) -> list:
+    """Device tensors of every problem of a batch: corpus and query CSR (row
+    lengths lognormal with the spec's mean and sd = cv * mean, clipped to
+    [1, min(d, 10 * mean)]; ids by Zipf(1.1) popularity with replacement), the
+    map pi and the problem's N, d and k (k capped at the corpus size)."""
+    import torch
+    probs = []
+    for sp in specs:
+        hi = int(min(sp.d, max(2, 10 * sp.mean)))
+        parts = []
+        for rows, sd_seed in ((sp.n, sp.seed), (sp.nq, sp.seed + 7919)):
+            if rows == 0:
+                parts.append((torch.zeros(1, dtype=torch.int32, device=device),
+                              torch.zeros(0, dtype=torch.int32, device=device)))
+                continue
+            (ip, ix), = list(device_corpus_chunks(rows, sp.d, sp.mean, cv * sp.mean, sd_seed, device,
+                                                  chunk_rows=rows, hi=hi))
+            parts.append((ip, ix))
+        pi = torch.from_numpy(random_map(sp.d, sp.N, SEED_PI + sp.seed)).to(device)
+        probs.append({"indptr": parts[0][0], "indices": parts[0][1], "q_indptr": parts[1][0],
+                      "q_indices": parts[1][1], "pi": pi, "d": sp.d, "N": sp.N, "k": min(k, sp.n)})
+    return probs

@@ -10,9 +10,9 @@
  *
  * Conventions shared by every entry point
  *   - All data pointers are DEVICE pointers on the current HIP device,
- *     allocated and owned by the caller. The library allocates nothing and
- *     keeps no state between calls apart from a per-device check that the
- *     device is a gfx950.
+ *     allocated and owned by the caller. The library allocates no device
+ *     memory and keeps no state between calls apart from a per-device check
+ *     that the device is a gfx950 (and the host-side batch handles, below).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Every call only enqueues work on that stream and returns before the
  *     work completes; results are valid once the stream has been synchronised.
@@ -164,6 +164,87 @@ bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint
                   const int32_t* popC, int64_t nC, int32_t N, int32_t measure, int32_t k,
                   int32_t* out_idx, float* out_score, void* workspace, size_t workspace_bytes,
                   void* stream);
+
+/*
+ * Batched problems — many independent corpora, each with its own queries,
+ * map pi, dimension d, width N and k, sketched (Section 3) and ranked
+ * (bs_topk's selection rule) together. The batch is recorded once into a HIP
+ * graph whose kernels each cover every problem (one sketch launch for all
+ * corpora and queries, then one launch per top-k stage and kernel variant)
+ * and replayed by bs_batch_run with a single hipGraphLaunch. Results equal
+ * those of bs_sketch and bs_topk on each problem alone, whatever the tile
+ * shapes.
+ *
+ * A batch handle is host memory the library allocates (bs_batch_destroy
+ * frees it, with its graph); device memory is the caller's workspace.
+ *
+ *   bs_batch_item   one problem; every pointer is a device pointer:
+ *     indptr, indices  corpus CSR (int32; n_rows >= 1 rows, nnz entries)
+ *     q_indptr, q_indices  query CSR (n_queries >= 0 rows, q_nnz entries)
+ *     pi               int32[d] map into [0, N)
+ *     sketches, popcounts      out: uint64[n_rows][N/64], int32[n_rows]
+ *     q_sketches, q_popcounts  out: uint64[n_queries][N/64], int32[n_queries]
+ *     out_idx, out_score       out: int32[n_queries][k], float[...] or NULL
+ *     1 <= k <= min(n_rows, BS_MAX_K); nnz and q_nnz < 2^31.
+ *   bs_batch_shape  the scan tile shape used for one width: 64-query groups
+ *     per wave (qpl) and the scan grid size in waves (0 = built-in rule);
+ *     ms is the time the autotuner measured for that width's top-k stages
+ *     (-1 if not tuned).
+ *
+ * bs_batch_workspace_size  device bytes for the items (0 if an item is
+ *     invalid); enough for every shape the autotuner can choose.
+ * bs_batch_create   plans the batch (measure as bs_topk), copies its tables
+ *     into the workspace (synchronously) and returns the handle; `shapes`
+ *     (may be NULL) fixes the shape per width, e.g. from an earlier
+ *     autotune. err_flags: int32[n_items] device words or NULL; the run
+ *     clears them, then ORs in item i's BS_FLAG_* bits (bs_sketch's rules).
+ * bs_batch_autotune  runs the batch's sketches once, then times every
+ *     candidate scan shape of each width (reps runs each, after a warm-up) on
+ *     that width's problems, keeps the fastest and re-plans. Synchronises
+ *     `stream`. Outputs hold a valid result afterwards.
+ * bs_batch_run      one graph launch of the whole batch on `stream` (the
+ *     graph is recorded at the first run after create or autotune).
+ * bs_batch_run_eager  the same kernels enqueued directly (no graph).
+ * bs_batch_shapes   writes up to cap shapes (one per distinct width,
+ *     ascending N) and returns the number of widths.
+ * bs_batch_graph_nodes  nodes of the recorded graph (0 before the first run).
+ * Calls on one handle must not overlap; the workspace must outlive it.
+ */
+typedef struct {
+  const int32_t* indptr;
+  const int32_t* indices;
+  int64_t n_rows, nnz;
+  const int32_t* q_indptr;
+  const int32_t* q_indices;
+  int64_t n_queries, q_nnz;
+  const int32_t* pi;
+  int64_t d;
+  int32_t N, k;
+  uint64_t* sketches;
+  int32_t* popcounts;
+  uint64_t* q_sketches;
+  int32_t* q_popcounts;
+  int32_t* out_idx;
+  float* out_score;
+} bs_batch_item;
+
+typedef struct {
+  int32_t N, qpl, waves;
+  float ms;
+} bs_batch_shape;
+
+typedef struct bs_batch bs_batch;
+
+size_t bs_batch_workspace_size(const bs_batch_item* items, int32_t n_items);
+bs_status bs_batch_create(const bs_batch_item* items, int32_t n_items, int32_t measure,
+                          const bs_batch_shape* shapes, int32_t n_shapes, void* workspace,
+                          size_t workspace_bytes, int32_t* err_flags, bs_batch** out);
+bs_status bs_batch_autotune(bs_batch* b, int32_t reps, void* stream);
+bs_status bs_batch_run(bs_batch* b, void* stream);
+bs_status bs_batch_run_eager(bs_batch* b, void* stream);
+int32_t bs_batch_shapes(const bs_batch* b, bs_batch_shape* out, int32_t cap);
+int32_t bs_batch_graph_nodes(const bs_batch* b);
+void bs_batch_destroy(bs_batch* b);
 
 /*
  * bs_pair_popcount — <a_s, b_s> = |A[ia[i]] AND B[ib[i]]| (Algorithm 1,

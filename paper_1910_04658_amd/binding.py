@@ -29,6 +29,25 @@ _lock = threading.Lock()
 _lib = None
 
 
+class BatchItem(ctypes.Structure):
+    """bs_batch_item (field order and types as in binsketch.h)."""
+    _fields_ = [("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("q_indptr", ctypes.c_void_p), ("q_indices", ctypes.c_void_p),
+                ("n_queries", ctypes.c_int64), ("q_nnz", ctypes.c_int64),
+                ("pi", ctypes.c_void_p), ("d", ctypes.c_int64),
+                ("N", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("sketches", ctypes.c_void_p), ("popcounts", ctypes.c_void_p),
+                ("q_sketches", ctypes.c_void_p), ("q_popcounts", ctypes.c_void_p),
+                ("out_idx", ctypes.c_void_p), ("out_score", ctypes.c_void_p)]
+
+
+class BatchShape(ctypes.Structure):
+    """bs_batch_shape."""
+    _fields_ = [("N", ctypes.c_int32), ("qpl", ctypes.c_int32), ("waves", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+
 class BinSketchError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -86,6 +105,23 @@ def load():
             L.bs_mlp_to_bf16.restype = ctypes.c_int
             L.bs_debug_set_topk_slab_capacity.argtypes = [i64]
             L.bs_debug_set_topk_slab_capacity.restype = ctypes.c_int
+            BI, BSh = ctypes.POINTER(BatchItem), ctypes.POINTER(BatchShape)
+            L.bs_batch_workspace_size.argtypes = [BI, i32]
+            L.bs_batch_workspace_size.restype = sz
+            L.bs_batch_create.argtypes = [BI, i32, i32, BSh, i32, p, sz, p, ctypes.POINTER(p)]
+            L.bs_batch_create.restype = ctypes.c_int
+            L.bs_batch_autotune.argtypes = [p, i32, p]
+            L.bs_batch_autotune.restype = ctypes.c_int
+            L.bs_batch_run.argtypes = [p, p]
+            L.bs_batch_run.restype = ctypes.c_int
+            L.bs_batch_run_eager.argtypes = [p, p]
+            L.bs_batch_run_eager.restype = ctypes.c_int
+            L.bs_batch_shapes.argtypes = [p, BSh, i32]
+            L.bs_batch_shapes.restype = i32
+            L.bs_batch_graph_nodes.argtypes = [p]
+            L.bs_batch_graph_nodes.restype = i32
+            L.bs_batch_destroy.argtypes = [p]
+            L.bs_batch_destroy.restype = None
             _lib = L
     return _lib
 
@@ -369,3 +405,87 @@ def mlp_train_step(master, w_bf16, adam_m, adam_v, step: int, lr: float, xa, xb,
 def mlp_to_bf16(master: torch.Tensor, w_bf16: torch.Tensor):
     st = load().bs_mlp_to_bf16(_ptr(master), _ptr(w_bf16), _stream())
     _check(st, "bs_mlp_to_bf16")
+
+
+class Batch:
+    """A batch of independent problems (bs_batch_*): each problem is a dict
+    with device tensors `indptr`, `indices` (corpus CSR, int32), `q_indptr`,
+    `q_indices` (query CSR), `pi` (int32[d]) and ints `d`, `N`, `k`. Output
+    tensors are allocated here, per problem: sketches, popcounts, q_sketches,
+    q_popcounts, idx, score. `shapes`: tuned shapes as returned by shapes()."""
+
+    def __init__(self, problems: list, measure="js", shapes=None, device=None):
+        L = load()
+        m = MEASURES[measure] if isinstance(measure, str) else int(measure)
+        dev = device if device is not None else problems[0]["indptr"].device
+        self.problems = problems
+        self.out = []
+        arr = (BatchItem * len(problems))()
+        for i, pb in enumerate(problems):
+            for name in ("indptr", "indices", "q_indptr", "q_indices", "pi"):
+                _need(pb[name], name, torch.int32, 1)
+            N, k = int(pb["N"]), int(pb["k"])
+            W = N // 64
+            n, nq = pb["indptr"].numel() - 1, pb["q_indptr"].numel() - 1
+            o = {"sketches": torch.empty((n, W), dtype=torch.int64, device=dev),
+                 "popcounts": torch.empty(n, dtype=torch.int32, device=dev),
+                 "q_sketches": torch.empty((max(nq, 0), W), dtype=torch.int64, device=dev),
+                 "q_popcounts": torch.empty(max(nq, 0), dtype=torch.int32, device=dev),
+                 "idx": torch.empty((max(nq, 0), k), dtype=torch.int32, device=dev),
+                 "score": torch.empty((max(nq, 0), k), dtype=torch.float32, device=dev)}
+            self.out.append(o)
+            it = arr[i]
+            it.indptr, it.indices = pb["indptr"].data_ptr(), pb["indices"].data_ptr()
+            it.n_rows, it.nnz = n, pb["indices"].numel()
+            it.q_indptr, it.q_indices = pb["q_indptr"].data_ptr(), pb["q_indices"].data_ptr()
+            it.n_queries, it.q_nnz = nq, pb["q_indices"].numel()
+            it.pi, it.d, it.N, it.k = pb["pi"].data_ptr(), int(pb["d"]), N, k
+            it.sketches, it.popcounts = o["sketches"].data_ptr(), o["popcounts"].data_ptr()
+            it.q_sketches, it.q_popcounts = o["q_sketches"].data_ptr(), o["q_popcounts"].data_ptr()
+            it.out_idx, it.out_score = o["idx"].data_ptr(), o["score"].data_ptr()
+        self._items = arr
+        nbytes = L.bs_batch_workspace_size(arr, len(problems))
+        if nbytes == 0:
+            raise BinSketchError(BS_ERR_ARG, "bs_batch_workspace_size")
+        self.workspace = _workspace(nbytes, dev)
+        self.err = torch.zeros(len(problems), dtype=torch.int32, device=dev)
+        sh = None
+        if shapes:
+            sh = (BatchShape * len(shapes))()
+            for j, x in enumerate(shapes):
+                sh[j].N, sh[j].qpl, sh[j].waves, sh[j].ms = int(x["N"]), int(x["qpl"]), int(x["waves"]), float(x.get("ms", -1))
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize(dev)
+        _check(L.bs_batch_create(arr, len(problems), m, sh, len(shapes) if shapes else 0, _ptr(self.workspace),
+                                 self.workspace.numel(), _ptr(self.err), ctypes.byref(h)), "bs_batch_create")
+        self._h = h
+
+    def autotune(self, reps: int = 3):
+        _check(load().bs_batch_autotune(self._h, int(reps), _stream()), "bs_batch_autotune")
+
+    def run(self):
+        _check(load().bs_batch_run(self._h, _stream()), "bs_batch_run")
+
+    def run_eager(self):
+        _check(load().bs_batch_run_eager(self._h, _stream()), "bs_batch_run_eager")
+
+    def shapes(self) -> list:
+        L = load()
+        n = L.bs_batch_shapes(self._h, None, 0)
+        arr = (BatchShape * max(n, 1))()
+        L.bs_batch_shapes(self._h, arr, n)
+        return [{"N": arr[j].N, "qpl": arr[j].qpl, "waves": arr[j].waves, "ms": arr[j].ms} for j in range(n)]
+
+    def graph_nodes(self) -> int:
+        return int(load().bs_batch_graph_nodes(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

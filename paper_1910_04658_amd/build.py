@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbinsketch.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["capi.cpp", "sketch.hip", "pairs.hip", "topk.hip", "mlp.hip"]
+SOURCES = ["capi.cpp", "sketch.hip", "pairs.hip", "topk.hip", "mlp.hip", "batch.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950",

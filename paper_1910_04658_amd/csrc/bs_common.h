@@ -59,6 +59,15 @@ __device__ __forceinline__ cptr<T> as_const(const T* p) {
 
 __device__ __forceinline__ uint32_t popc32(uint32_t x) { return __builtin_popcount(x); }
 
+// acc + popcount(x) as one v_bcnt_u32_b32 (bit count with accumulate). The
+// compiler otherwise may split long count chains into separate counts plus
+// three-input adds, half an instruction more per word.
+__device__ __forceinline__ uint32_t bcnt_add(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
 // Order-preserving map float -> uint32 (larger float -> larger key). -0.0 is
 // first turned into +0.0 so that the two zeros compare equal, as IEEE says.
 __device__ __forceinline__ uint32_t float_key(float f) {

@@ -39,6 +39,9 @@ hipEvent_t take_event() {
 ScopedTiming::ScopedTiming(const char* name, hipStream_t s) : name_(name), s_(s) {
   std::lock_guard<std::mutex> lock(g_tmu);
   if (!g_timing) return;
+  // launches recorded into a graph are timed only as a whole, by the caller
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   start_ = take_event();
   stop_ = take_event();
   if (start_ && stop_) (void)hipEventRecord(start_, s_);

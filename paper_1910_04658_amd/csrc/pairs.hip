@@ -138,7 +138,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
         const int64_t ar = (a0 + t < a_end) ? a0 + t : a_end - 1;
         const cptr<uint32_t> arow = as_const(a.A + (size_t)ar * W32 + c * WC);
 #pragma unroll
-        for (int w = 0; w < WC; ++w) acc[t] += popc32(arow[w] & bw[w]);
+        for (int w = 0; w < WC; ++w) acc[t] = bcnt_add(arow[w] & bw[w], acc[t]);
       }
     }
 #pragma unroll

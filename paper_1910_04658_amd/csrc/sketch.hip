@@ -21,7 +21,13 @@
 //   * The window's sketches are contiguous in the output, so they leave LDS
 //     as one coalesced run of 64-bit non-temporal stores; popcounts are summed
 //     per row in LDS on the way out.
+#include <string.h>
+
+#include <memory>
+#include <vector>
+
 #include "bs_common.h"
+#include "sketch_group.h"
 
 namespace bs {
 namespace {
@@ -47,16 +53,14 @@ struct SketchArgs {
   int32_t stride;  // LDS words per wave: G*W32 + G
 };
 
-__global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_csr_kernel(SketchArgs a) {
-  extern __shared__ uint32_t lds[];
-  const int wid = threadIdx.x / kWave;
+// One window of G rows by one wave; `sk` is the wave's LDS stage
+// (a.stride words). Wave-level synchronisation only.
+__device__ __forceinline__ void sketch_window(const SketchArgs& a, int64_t wave, uint32_t* sk) {
   const int lane = threadIdx.x % kWave;
-  const int64_t wave = (int64_t)blockIdx.x * kWavesPerBlock + wid;
   const int64_t r0 = wave * a.G;
   if (r0 >= a.n_rows) return;
   const int g = (int)(a.n_rows - r0 < a.G ? a.n_rows - r0 : a.G);
   const int W32 = a.W32;
-  uint32_t* sk = lds + (size_t)wid * a.stride;
   uint32_t* cnt = sk + (size_t)a.G * W32;
 
   // Row pointers of the window: lane l holds indptr[r0 + l] for l <= g.
@@ -139,6 +143,59 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_csr_kernel(Sket
     if (lane < g) a.pop[r0 + lane] = (int32_t)cnt[lane];
   }
   if (a.err && errbits) atomicOr(a.err, (int32_t)errbits);
+  // the stage may be reused by this wave's next window
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_csr_kernel(SketchArgs a) {
+  extern __shared__ uint32_t lds[];
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  sketch_window(a, (int64_t)blockIdx.x * kWavesPerBlock + wid, lds + (size_t)wid * a.stride);
+}
+
+// Many independent sketch problems (different maps, widths and sizes) in one
+// launch: the windows of all items form one list; wave w of the grid takes
+// windows w, w + (waves in the grid), ... and finds each window's item by a
+// binary search over the items' first-window offsets.
+__device__ __forceinline__ SketchArgs load_sketch_args(const SketchArgs* p) {
+  const cptr<SketchArgs> c = as_const(p);
+  SketchArgs a;
+  a.indptr = c->indptr;
+  a.indices = c->indices;
+  a.pi = c->pi;
+  a.out32 = c->out32;
+  a.pop = c->pop;
+  a.err = c->err;
+  a.n_rows = c->n_rows;
+  a.nnz = c->nnz;
+  a.d = c->d;
+  a.N = c->N;
+  a.W32 = c->W32;
+  a.G = c->G;
+  a.stride = c->stride;
+  return a;
+}
+
+__global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_group_kernel(const SketchArgs* items,
+                                                                            const int64_t* woff, int32_t n,
+                                                                            int64_t total, int32_t wave_words) {
+  extern __shared__ uint32_t lds[];
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  uint32_t* sk = lds + (size_t)wid * wave_words;
+  const cptr<int64_t> off = as_const(woff);
+  const int64_t step = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t w = (int64_t)blockIdx.x * kWavesPerBlock + wid; w < total; w += step) {
+    int lo = 0, hi = n - 1;  // last item whose first window is <= w
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= w) lo = mid;
+      else hi = mid - 1;
+    }
+    const SketchArgs a = load_sketch_args(items + lo);
+    sketch_window(a, w - off[lo], sk);
+  }
 }
 
 // ---- map-in-LDS variant ---------------------------------------------------
@@ -333,6 +390,108 @@ inline int map_bits(int32_t N) {
 }
 inline int64_t map_table_words(int64_t d, int32_t N) { return (d + 31) / 32 * map_bits(N) + 1; }
 }  // namespace
+}  // namespace bs
+
+namespace bs {
+
+bs_status sketch_item_check(const SketchItem& it) {
+  if (it.n_rows < 0 || it.nnz < 0 || it.nnz > INT32_MAX || it.d < 1 || it.d > INT32_MAX || !valid_width(it.N))
+    return BS_ERR_ARG;
+  if (!it.indptr || !it.pi || (!it.indices && it.nnz > 0) || (!it.sketches && it.n_rows > 0)) return BS_ERR_NULL;
+  return BS_OK;
+}
+
+struct SketchGroup {
+  const SketchArgs* items = nullptr;
+  const int64_t* woff = nullptr;
+  int32_t n = 0;
+  int64_t total = 0;
+  int32_t wave_words = 0;
+  int64_t grid = 0;
+};
+
+size_t sketch_group_meta_bytes(int32_t n) {
+  if (n < 0) return 0;
+  return align256((size_t)n * sizeof(SketchArgs)) + align256(((size_t)n + 1) * sizeof(int64_t));
+}
+
+bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, size_t meta_bytes, bool persistent,
+                              SketchGroup** out) {
+  if (!out) return BS_ERR_NULL;
+  *out = nullptr;
+  if (n < 0) return BS_ERR_ARG;
+  if (n > 0 && (!items || !meta)) return BS_ERR_NULL;
+  if (meta_bytes < sketch_group_meta_bytes(n) || (reinterpret_cast<uintptr_t>(meta) & 255)) return BS_ERR_WORKSPACE;
+  std::vector<SketchArgs> args(n);
+  std::vector<int64_t> woff((size_t)n + 1);
+  int64_t total = 0;
+  int32_t wave_words = 1;
+  for (int32_t i = 0; i < n; ++i) {
+    const bs_status st = sketch_item_check(items[i]);
+    if (st != BS_OK) return st;
+    SketchArgs& a = args[i];
+    a.indptr = items[i].indptr;
+    a.indices = items[i].indices;
+    a.pi = items[i].pi;
+    a.out32 = reinterpret_cast<uint32_t*>(items[i].sketches);
+    a.pop = items[i].popcounts;
+    a.err = items[i].err;
+    a.n_rows = items[i].n_rows;
+    a.nnz = items[i].nnz;
+    a.d = items[i].d;
+    a.N = items[i].N;
+    a.W32 = items[i].N / 32;
+    int G = kStageWords / a.W32;
+    a.G = G < 1 ? 1 : (G > kMaxRowsPerWave ? kMaxRowsPerWave : G);
+    a.stride = a.G * a.W32 + a.G;
+    wave_words = a.stride > wave_words ? a.stride : wave_words;
+    woff[i] = total;
+    total += (a.n_rows + a.G - 1) / a.G;
+  }
+  woff[n] = total;
+  std::unique_ptr<SketchGroup> g(new SketchGroup);
+  char* m = static_cast<char*>(meta);
+  std::vector<char> host(sketch_group_meta_bytes(n), 0);
+  const size_t args_bytes = align256((size_t)n * sizeof(SketchArgs));
+  if (n > 0) memcpy(host.data(), args.data(), (size_t)n * sizeof(SketchArgs));
+  memcpy(host.data() + args_bytes, woff.data(), woff.size() * sizeof(int64_t));
+  if (!host.empty() && hipMemcpy(meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return BS_ERR_HIP;
+  g->items = reinterpret_cast<const SketchArgs*>(m);
+  g->woff = reinterpret_cast<const int64_t*>(m + args_bytes);
+  g->n = n;
+  g->total = total;
+  g->wave_words = wave_words;
+  const int64_t blocks = (total + kWavesPerBlock - 1) / kWavesPerBlock;
+  g->grid = blocks;
+  if (persistent && blocks > 0) {
+    int lds_max = 0, n_cu = 0;
+    device_limits(&lds_max, &n_cu);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)sketch_group_kernel, kWavesPerBlock * kWave,
+                                                      (size_t)kWavesPerBlock * wave_words * 4) != hipSuccess ||
+        nb < 1)
+      nb = 1;
+    const int64_t cap = (int64_t)nb * (n_cu > 0 ? n_cu : 1);
+    if (g->grid > cap) g->grid = cap;
+  }
+  *out = g.release();
+  return BS_OK;
+}
+
+bs_status sketch_group_launch(const SketchGroup* g, hipStream_t s) {
+  if (!g) return BS_ERR_NULL;
+  if (g->total == 0) return BS_OK;
+  if (g->grid > INT32_MAX) return BS_ERR_ARG;
+  ScopedTiming timing("sketch_group", s);
+  hipLaunchKernelGGL(sketch_group_kernel, dim3((unsigned)g->grid), dim3(kWavesPerBlock * kWave),
+                     (size_t)kWavesPerBlock * g->wave_words * 4, s, g->items, g->woff, g->n, g->total,
+                     g->wave_words);
+  return launch_status();
+}
+
+void sketch_group_destroy(SketchGroup* g) { delete g; }
+
 }  // namespace bs
 
 extern "C" size_t bs_sketch_workspace_size(int64_t d, int32_t N) {

@@ -28,8 +28,13 @@
 //     few blocks and selected the same way. Results never depend on which path
 //     ran.
 #include <float.h>
+#include <string.h>
+
+#include <memory>
+#include <vector>
 
 #include "bs_common.h"
+#include "topk_group.h"
 
 namespace bs {
 
@@ -59,12 +64,14 @@ struct QConst {  // per-query constants written by the sample pass
 struct Plan {
   int64_t S, stride, F;
   int64_t qpl, ngrp, nqb4, n_slabs, slab, scap, kmax;  // scan geometry
+  int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
+  int64_t lds_keys;                                   // select: candidate keys held in LDS
   size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_slots, off_qovf, off_keys,
       off_scratch, off_mtab, off_ovf, off_skeys, total;
 };
 
-Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
+Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tune) {
   Plan p;
   // sample size: 4,096 rows, growing as nC/256 up to 15,360 for large corpora
   // (the candidate count per query is about k * nC / S)
@@ -76,19 +83,25 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   const int W32 = N / 32;
   const bool pow2 = (W32 & (W32 - 1)) == 0;
   p.qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && W32 == 16) ? 2 : 1);
+  if (tune.qpl == 1 || (tune.qpl == 2 && pow2 && W32 <= 16) || (tune.qpl == 4 && pow2 && W32 <= 16))
+    p.qpl = tune.qpl;
   const int64_t nqb = (nQ + 63) / 64;
   p.ngrp = (nqb + p.qpl - 1) / p.qpl;
   p.nqb4 = (p.ngrp + 3) / 4;
   // A batch of at most 64 queries leaves most lanes of a query-lane wave
   // idle and streams the corpus through the scalar unit: it is scanned with
   // corpus rows on the lanes instead, each wave over a run of 64-row tiles.
-  p.rows = nQ <= kRowsMaxQ && pow2 && W32 <= 128;
+  const bool rows_ok = nQ <= kRowsMaxQ && pow2 && W32 <= 128;
+  p.rows = rows_ok && tune.rows != 0;
+  if (p.rows) p.qpl = 1;
   if (p.rows) {
+    const int64_t waves = tune.waves > 0 ? tune.waves : kRowWaves;
     const int64_t tiles = (nC + kWave - 1) / kWave;
-    const int64_t tpw = (tiles + kRowWaves - 1) / kRowWaves;
+    const int64_t tpw = (tiles + waves - 1) / waves;
     p.slab = tpw * kWave;
   } else {
-    int64_t n_slabs = p.ngrp > 0 ? (kScanWaves + p.ngrp - 1) / p.ngrp : 1;
+    const int64_t waves = tune.waves > 0 ? tune.waves : kScanWaves;
+    int64_t n_slabs = p.ngrp > 0 ? (waves + p.ngrp - 1) / p.ngrp : 1;
     if (n_slabs > nC) n_slabs = nC;
     if (n_slabs < 1) n_slabs = 1;
     p.slab = (nC + n_slabs - 1) / n_slabs;
@@ -106,6 +119,22 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
     p.scap = 0;
   }
   p.kmax = p.S + p.n_slabs * p.scap;
+  // sample-score grid: 256-row blocks x query blocks, ~2k blocks in all
+  p.s_rblocks = (p.S + kThreads - 1) / kThreads;
+  p.s_nqb = (2048 + p.s_rblocks - 1) / p.s_rblocks;
+  if (p.s_nqb > nQ) p.s_nqb = nQ;
+  if (p.s_nqb < 1) p.s_nqb = 1;
+  p.s_qb = (nQ + p.s_nqb - 1) / p.s_nqb;
+  if (p.s_qb < 1) p.s_qb = 1;
+  p.s_nqb = (nQ + p.s_qb - 1) / p.s_qb;
+  // LDS of the select kernel: room for 1.5x the expected candidate count
+  // (k * nC / S) so that several blocks share a CU; a query with more
+  // candidates selects in its global buffer instead
+  {
+    const double expect = p.S > 0 ? (double)k * (double)nC / (double)p.S : 0.0;
+    int64_t lk = ((int64_t)(1.5 * expect) + 512 + 255) / 256 * 256;
+    p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
+  }
   // fallback blocks: at most 16, and at most 256 MB of whole-corpus key scratch
   int64_t F = (INT64_C(256) << 20) / (8 * nC);
   F = F < 1 ? 1 : (F > kFallbackBlocks ? kFallbackBlocks : F);
@@ -246,9 +275,60 @@ struct TopkArgs {
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
   float* __restrict__ out_score;   // [nQ][k] or null
-  int64_t nQ, nQp, nC, S, stride, n_slabs, slab, nqb4, scap, kmax;
+  int64_t nQ, nQp, nC, S, stride, n_slabs, slab, nqb4, scap, kmax, lds_keys;
+  int64_t s_rblocks, s_nqb, s_qb;  // sample-score grid: row blocks x query blocks of s_qb queries
+  int64_t F;                       // fallback blocks
   int32_t N, W32, k, kpad;
+  int32_t qpl, rows;               // scan variant: queries per lane, row-lane scan
 };
+
+// Member-wise copy through the constant address space, so that the fields of
+// a per-corpus argument block read by a grouped kernel land in scalar
+// registers (the hot loops take their row pointers from them).
+__device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
+  const cptr<TopkArgs> c = as_const(p);
+  TopkArgs a;
+  a.Q = c->Q;
+  a.C = c->C;
+  a.t32 = c->t32;
+  a.popQ = c->popQ;
+  a.popC = c->popC;
+  a.qc = c->qc;
+  a.cnts = c->cnts;
+  a.cands = c->cands;
+  a.scnt = c->scnt;
+  a.slots = c->slots;
+  a.qovf = c->qovf;
+  a.keys = c->keys;
+  a.scratch = c->scratch;
+  a.mtab = c->mtab;
+  a.ovf = c->ovf;
+  a.skeys = c->skeys;
+  a.out_idx = c->out_idx;
+  a.out_score = c->out_score;
+  a.nQ = c->nQ;
+  a.nQp = c->nQp;
+  a.nC = c->nC;
+  a.S = c->S;
+  a.stride = c->stride;
+  a.n_slabs = c->n_slabs;
+  a.slab = c->slab;
+  a.nqb4 = c->nqb4;
+  a.scap = c->scap;
+  a.kmax = c->kmax;
+  a.lds_keys = c->lds_keys;
+  a.s_rblocks = c->s_rblocks;
+  a.s_nqb = c->s_nqb;
+  a.s_qb = c->s_qb;
+  a.F = c->F;
+  a.N = c->N;
+  a.W32 = c->W32;
+  a.k = c->k;
+  a.kpad = c->kpad;
+  a.qpl = c->qpl;
+  a.rows = c->rows;
+  return a;
+}
 
 // x_ab of one query (words in LDS) against one corpus row (global).
 __device__ __forceinline__ int32_t and_popcount_row(const uint64_t* qw, const uint64_t* __restrict__ crow,
@@ -304,7 +384,7 @@ __device__ QConst make_qconst(float tau, float Tq, int32_t xq) {
 // the scalar unit, and the keys of one query land in 64 consecutive slots.
 // W32T: words per row when it is a compile-time constant, else 0 (generic).
 template <int M, int W32T, bool LDS_LUT>
-__global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a, int64_t qb_size) {
+__device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut_s[];
   const float* lut = a.t32;
   if (LDS_LUT) {
@@ -312,9 +392,9 @@ __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a
     __syncthreads();
     lut = lut_s;
   }
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;  // sample index
-  const int64_t q_begin = (int64_t)blockIdx.y * qb_size;
-  const int64_t q_end = q_begin + qb_size < a.nQ ? q_begin + qb_size : a.nQ;
+  const int64_t i = bx * kThreads + threadIdx.x;  // sample index
+  const int64_t q_begin = by * a.s_qb;
+  const int64_t q_end = q_begin + a.s_qb < a.nQ ? q_begin + a.s_qb : a.nQ;
   const bool i_ok = i < a.S;
   const int64_t row = (i_ok ? i : a.S - 1) * a.stride;
   const int W32 = W32T ? W32T : a.W32;
@@ -332,7 +412,7 @@ __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a
     uint32_t acc = 0;
     if (W32T) {
 #pragma unroll
-      for (int w = 0; w < R; ++w) acc += popc32(qrow[w] & cw[w]);
+      for (int w = 0; w < R; ++w) acc = bcnt_add(qrow[w] & cw[w], acc);
     } else {
       for (int w = 0; w < W32; w += 2) {
         const uint2 c2 = *reinterpret_cast<const uint2*>(crow + w);
@@ -350,14 +430,13 @@ __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(TopkArgs a
 // 1b. Per query: the k-th best sample key (LDS radix select), the sample rows
 // scoring at least that, and the per-query constants of the scan filter.
 template <int M>
-__global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(TopkArgs a) {
+__device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint32_t keys[];  // [S]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint32_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
-  const int64_t q = blockIdx.x;
   const uint32_t* src = a.skeys + (size_t)q * a.S;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) keys[i] = src[i];
   if (threadIdx.x == 0) nsel = 0;
@@ -389,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(TopkArgs a
 constexpr int kBoundX = 64;  // table rows (x_c values) per block of the threshold kernel
 
 template <int M, bool LDS_LUT>
-__global__ __launch_bounds__(kThreads) void topk_bound_kernel(TopkArgs a) {
+__device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut_s[];
   const float* lut = a.t32;
   if (LDS_LUT) {
@@ -397,13 +476,13 @@ __global__ __launch_bounds__(kThreads) void topk_bound_kernel(TopkArgs a) {
     __syncthreads();
     lut = lut_s;
   }
-  const int64_t qi = (int64_t)blockIdx.x * kWave + threadIdx.x % kWave;
-  if (qi >= a.nQp) return;
+  const int64_t qi = bx * kWave + threadIdx.x % kWave;
+  if (qi >= a.nQp) return;  // block-uniform (nQp is a multiple of 64)
   QConst k = {};
   const bool q_ok = qi < a.nQ;
   if (q_ok) k = a.qc[qi];
   for (int r = threadIdx.x / kWave; r < kBoundX; r += kThreads / kWave) {
-    const int xc = blockIdx.y * kBoundX + r;
+    const int xc = (int)by * kBoundX + r;
     if (xc > a.N) break;
     uint16_t m = 65535;
     if (q_ok) {
@@ -432,12 +511,11 @@ __global__ __launch_bounds__(kThreads) void topk_bound_kernel(TopkArgs a) {
 // of a block take four query groups of the same slab, so they read the same
 // corpus words (scalar-cache hits after the first). W32T: words per row.
 template <int W32T, int QPL>
-__global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t n_slabs, int64_t slab,
-                                                             int64_t nqb4) {
+__device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
+  const int64_t slab = a.slab, nqb4 = a.nqb4;
   constexpr int PS = W32T < 32 ? W32T : 32;  // words per scalar piece
   constexpr int P = W32T / PS;               // pieces per row
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  const int64_t bid = blockIdx.x;
+  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t sl = bid / nqb4;
   const int64_t qg0 = ((bid % nqb4) * (kThreads / kWave) + wid) * QPL;  // first 64-query group
   const int64_t c_begin = sl * slab;
@@ -510,7 +588,7 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
 #pragma unroll
       for (int j = 0; j < QPL; ++j) {
 #pragma unroll
-        for (int w = 0; w < PS; ++w) acc[j] += popc32(cur[w] & qw[j][p * PS + w]);
+        for (int w = 0; w < PS; ++w) acc[j] = bcnt_add(cur[w] & qw[j][p * PS + w], acc[j]);
       }
 #pragma unroll
       for (int w = 0; w < PS; ++w) cur[w] = nxt[w];
@@ -540,10 +618,9 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(TopkArgs a, int64_t
 // Generic widths (N not a power of two, or N > 4096): query words re-read per
 // chunk of WC words; correct for every width, tuned for none.
 template <int WC>
-__global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a, int64_t n_slabs, int64_t slab,
-                                                                     int64_t nqb4) {
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  const int64_t bid = blockIdx.x;
+__device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid) {
+  const int64_t slab = a.slab, nqb4 = a.nqb4;
+  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int64_t sl = bid / nqb4;
   const int64_t qb = (bid % nqb4) * (kThreads / kWave) + wid;
   const int64_t q = qb * kWave + lane;
@@ -568,7 +645,7 @@ __global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(TopkArgs a,
       for (int w = 0; w < WC; ++w) qw[w] = qrow[ch * WC + w];
       const cptr<uint32_t> cr = as_const(C32 + (size_t)c * W32 + ch * WC);
 #pragma unroll
-      for (int w = 0; w < WC; ++w) acc += popc32(cr[w] & qw[w]);
+      for (int w = 0; w < WC; ++w) acc = bcnt_add(cr[w] & qw[w], acc);
     }
     const int32_t xc = as_const(a.popC)[c];
     const uint16_t m = mt[(size_t)xc * a.nQp];
@@ -600,14 +677,14 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
 // lane j of the counter register holds query j's running count. Survivors
 // are stored as final selection keys (the score is at hand here).
 template <int M, int W32T>
-__global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(TopkArgs a) {
+__device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
   extern __shared__ float lut[];  // T[0..N]
   for (int x = threadIdx.x; x <= a.N; x += kThreads) lut[x] = a.t32[x];
   __syncthreads();
   constexpr int PS = W32T < 32 ? W32T : 32;  // query words per scalar piece
   const int lane = threadIdx.x % kWave;
-  const int64_t sl = (int64_t)blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
-  if (sl >= a.n_slabs) return;  // wave-uniform
+  const int64_t sl = bid * (kThreads / kWave) + __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (sl >= a.n_slabs) return;  // wave-uniform; no block barrier follows
   const int64_t r_begin = sl * a.slab;
   const int64_t r_end = r_begin + a.slab < a.nC ? r_begin + a.slab : a.nC;
   const int nQ = (int)a.nQ;
@@ -652,7 +729,7 @@ __global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(TopkArgs a) {
       for (int p = 0; p < W32T / PS; ++p) {
         const cptr<uint32_t> qw = as_const(Q32 + (size_t)q * W32T + p * PS);
 #pragma unroll
-        for (int w = 0; w < PS; ++w) acc += popc32(row[p * PS + w] & qw[w]);
+        for (int w = 0; w < PS; ++w) acc = bcnt_add(row[p * PS + w] & qw[w], acc);
       }
       float bound = fmaf(qc[q].Tq + Tc, qc[q].A, qc[q].C);
       if (M == BS_COSINE) bound = fmaf(sTc, qc[q].B, bound);
@@ -720,8 +797,8 @@ __device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, c
 // Slot entries of the query-lane scan are (x_ab << 32 | row) and are scored
 // here (RAW); the row-lane scan and the sample pass store final keys.
 template <int M, bool RAW>
-__global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
-  extern __shared__ uint64_t sm[];  // sel[kpad], then keys[kSelectLdsKeys]
+__device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
+  extern __shared__ uint64_t sm[];  // sel[kpad], then keys[lds_keys]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint32_t off[kSelChunk + 1];
@@ -730,8 +807,7 @@ __global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
   __shared__ uint32_t nsel;
   __shared__ uint32_t total_s;
   constexpr int PER = kSelChunk / kThreads;
-  const int64_t q = blockIdx.x;
-  if (a.qovf[q]) {  // a slab overflowed its slots: hand the query to the fallback kernel
+  if (a.qovf[q]) {  // block-uniform  // a slab overflowed its slots: hand the query to the fallback kernel
     if (threadIdx.x == 0) a.ovf[1 + atomicAdd(a.ovf, 1)] = (int32_t)q;
     return;
   }
@@ -745,7 +821,7 @@ __global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
   const int64_t ns = a.cnts[q];
   const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  uint64_t* keys = n <= kSelectLdsKeys ? sm + a.kpad : a.keys + (size_t)q * a.kmax;
+  uint64_t* keys = n <= a.lds_keys ? sm + a.kpad : a.keys + (size_t)q * a.kmax;
   const int32_t xq = a.popQ[q];
   const float Tq = a.t32[xq];
   // 2. compact: the sample's candidates, then every slab's slots in slab order.
@@ -792,7 +868,7 @@ __global__ __launch_bounds__(kThreads) void topk_select_kernel(TopkArgs a) {
 
 // ---- fallback: whole-corpus selection for overflowed queries ----------------
 template <int M>
-__global__ __launch_bounds__(kThreads) void topk_fallback_kernel(TopkArgs a) {
+__device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int64_t nb) {
   extern __shared__ uint64_t sm[];  // sel[kpad], then qw[W64]
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
@@ -802,9 +878,9 @@ __global__ __launch_bounds__(kThreads) void topk_fallback_kernel(TopkArgs a) {
   const int W64 = a.W32 / 2;
   uint64_t* sel = sm;
   uint64_t* qw = sm + a.kpad;
-  uint64_t* keys = a.scratch + (size_t)blockIdx.x * a.nC;
+  uint64_t* keys = a.scratch + (size_t)b * a.nC;
   const int32_t n_ovf = a.ovf[0];
-  for (int32_t i = blockIdx.x; i < n_ovf; i += gridDim.x) {
+  for (int64_t i = b; i < n_ovf; i += nb) {
     const int64_t q = a.ovf[1 + i];
     const uint64_t* qrow = a.Q + (size_t)q * W64;
     for (int w = threadIdx.x; w < W64; w += kThreads) qw[w] = qrow[w];
@@ -822,111 +898,257 @@ __global__ __launch_bounds__(kThreads) void topk_fallback_kernel(TopkArgs a) {
   }
 }
 
-template <int M>
-bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
-  const int W64 = a.W32 / 2;
-  // 1. sample
-  {
-    ScopedTiming timing("topk_sample", s);
-    const bool lds_lut = a.N <= 16384;
-    const int64_t rblocks = (p.S + kThreads - 1) / kThreads;
-    int64_t nqb = (2048 + rblocks - 1) / rblocks;  // ~2k blocks
-    if (nqb > a.nQ) nqb = a.nQ;
-    const int64_t qb_size = (a.nQ + nqb - 1) / nqb;
-    nqb = (a.nQ + qb_size - 1) / qb_size;
-    const dim3 g1((unsigned)rblocks, (unsigned)nqb);
-    const size_t l1 = lds_lut ? (size_t)(a.N + 1) * 4 : 0;
-    const int W32 = a.W32;
-#define BS_SAMPLE(w)                                                                                       \
-  do {                                                                                                     \
-    if (lds_lut)                                                                                           \
-      hipLaunchKernelGGL((topk_sample_scores_kernel<M, w, true>), g1, dim3(kThreads), l1, s, a, qb_size);  \
-    else                                                                                                   \
-      hipLaunchKernelGGL((topk_sample_scores_kernel<M, w, false>), g1, dim3(kThreads), l1, s, a, qb_size); \
-  } while (0)
-    switch (W32) {
-      case 2: BS_SAMPLE(2); break;
-      case 4: BS_SAMPLE(4); break;
-      case 8: BS_SAMPLE(8); break;
-      case 16: BS_SAMPLE(16); break;
-      case 32: BS_SAMPLE(32); break;
-      case 64: BS_SAMPLE(64); break;
-      case 128: BS_SAMPLE(128); break;
-      default: BS_SAMPLE(0); break;
-    }
-#undef BS_SAMPLE
-    hipLaunchKernelGGL((topk_sample_select_kernel<M>), dim3((unsigned)a.nQ), dim3(kThreads), (size_t)p.S * 4, s,
-                       a);
+// ---- grouped launches ---------------------------------------------------------
+// Every stage kernel runs a list of virtual blocks: block vb of the launch
+// belongs to item i with voff[i] <= vb < voff[i + 1] and is that item's local
+// block vb - voff[i]. A launch of one item carries its arguments inline
+// (items == null). With fewer hardware blocks than virtual blocks the grid is
+// persistent: each block walks vb = blockIdx.x, + gridDim.x, ...; every body
+// returns only at points where the whole block or a whole wave is done with
+// block barriers, and a barrier separates consecutive virtual blocks.
+struct GroupArgs {
+  const TopkArgs* items;  // [n] argument blocks in device memory, or null
+  const int64_t* voff;    // [n + 1]
+  int64_t total;          // virtual blocks
+  int32_t n;
+  TopkArgs one;           // the single item when items is null
+};
+
+__device__ __forceinline__ int64_t group_item(const GroupArgs& g, int64_t vb, TopkArgs& a) {
+  if (!g.items) {
+    a = g.one;
+    return vb;
   }
-  // 2. thresholds, then scan the rest of the corpus
-  if (p.S < a.nC && p.rows) {
-    ScopedTiming timing("topk_scan", s);
-    const dim3 g((unsigned)((p.n_slabs + kThreads / kWave - 1) / (kThreads / kWave))), b(kThreads);
-    const size_t lds = (size_t)(a.N + 1) * 4;
-    switch (a.W32) {
-      case 2: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 2>), g, b, lds, s, a); break;
-      case 4: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 4>), g, b, lds, s, a); break;
-      case 8: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 8>), g, b, lds, s, a); break;
-      case 16: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 16>), g, b, lds, s, a); break;
-      case 32: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 32>), g, b, lds, s, a); break;
-      case 64: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 64>), g, b, lds, s, a); break;
-      default: hipLaunchKernelGGL((topk_scan_rows_kernel<M, 128>), g, b, lds, s, a); break;
-    }
-  } else if (p.S < a.nC) {
-    {
-      ScopedTiming timing("topk_bound", s);
-      const dim3 g((unsigned)(a.nQp / kWave), (unsigned)((a.N + 1 + kBoundX - 1) / kBoundX));
-      if (a.N <= 16384)
-        hipLaunchKernelGGL((topk_bound_kernel<M, true>), g, dim3(kThreads), (size_t)(a.N + 1) * 4, s, a);
-      else
-        hipLaunchKernelGGL((topk_bound_kernel<M, false>), g, dim3(kThreads), 0, s, a);
-    }
-    const int W32 = a.W32;
-    const bool pow2 = (W32 & (W32 - 1)) == 0;
-    const int64_t n_slabs = p.n_slabs, slab = p.slab, nqb4 = p.nqb4;
-    const int64_t grid = n_slabs * nqb4;
-    if (grid > INT32_MAX) return BS_ERR_ARG;
-    ScopedTiming timing("topk_scan", s);
-    const dim3 g((unsigned)grid), b(kThreads);
-    if (pow2 && W32 <= 128) {
+  const cptr<int64_t> off = as_const(g.voff);
+  int lo = 0, hi = g.n - 1;  // last item whose first block is <= vb (items with no blocks are skipped)
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= vb) lo = mid;
+    else hi = mid - 1;
+  }
+  a = load_args(g.items + lo);
+  return vb - off[lo];
+}
+
+// ONE: a single item, one hardware block per virtual block (no loop, no
+// argument lookup: the leanest code for the hot loops' register budget).
+#define BS_GROUP_LOOP(BODY)                                           \
+  if (ONE) {                                                          \
+    const TopkArgs& a = g.one;                                        \
+    const int64_t lb = blockIdx.x;                                    \
+    BODY;                                                             \
+    return;                                                           \
+  }                                                                   \
+  for (int64_t vb = blockIdx.x; vb < g.total; vb += gridDim.x) {      \
+    if (vb != (int64_t)blockIdx.x) __syncthreads();                   \
+    TopkArgs a;                                                       \
+    const int64_t lb = group_item(g, vb, a);                          \
+    BODY;                                                             \
+  }
+
+template <bool ONE, int M, int W32T, bool LDS_LUT>
+__global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((sample_scores_body<M, W32T, LDS_LUT>(a, lb % a.s_rblocks, lb / a.s_rblocks)))
+}
+template <bool ONE, int M>
+__global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((sample_select_body<M>(a, lb)))
+}
+template <bool ONE, int M, bool LDS_LUT>
+__global__ __launch_bounds__(kThreads) void topk_bound_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((bound_body<M, LDS_LUT>(a, lb % (a.nQp / kWave), lb / (a.nQp / kWave))))
+}
+template <bool ONE, int W32T, int QPL>
+__global__ __launch_bounds__(kThreads) void topk_scan_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((scan_body<W32T, QPL>(a, lb)))
+}
+template <bool ONE, int WC>
+__global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((scan_generic_body<WC>(a, lb)))
+}
+template <bool ONE, int M, int W32T>
+__global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((scan_rows_body<M, W32T>(a, lb)))
+}
+template <bool ONE, int M, bool RAW>
+__global__ __launch_bounds__(kThreads) void topk_select_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((select_body<M, RAW>(a, lb)))
+}
+template <bool ONE, int M>
+__global__ __launch_bounds__(kThreads) void topk_fallback_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((fallback_body<M>(a, lb, a.F)))
+}
+#undef BS_GROUP_LOOP
+
+enum Stage { kStSample = 0, kStSampleSelect, kStBound, kStScan, kStSelect, kStFallback, kStages };
+const char* const kStageTimer[kStages] = {"topk_sample", "topk_sample", "topk_bound",
+                                          "topk_scan",   "topk_select", "topk_fallback"};
+
+// Virtual blocks of one item in one stage (0: the stage does not run).
+int64_t stage_blocks(const TopkArgs& a, int st) {
+  const bool scan = a.S < a.nC;
+  switch (st) {
+    case kStSample: return a.s_rblocks * a.s_nqb;
+    case kStSampleSelect: return a.nQ;
+    case kStBound: return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 1 + kBoundX - 1) / kBoundX) : 0;
+    case kStScan: return scan ? (a.rows ? (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave)
+                                        : a.n_slabs * a.nqb4)
+                              : 0;
+    case kStSelect: return a.nQ;
+    default: return scan ? a.F : 0;
+  }
+}
+
+// Dynamic LDS bytes of one item in one stage.
+size_t stage_lds(const TopkArgs& a, int st) {
+  const bool lds_lut = a.N <= 16384;
+  switch (st) {
+    case kStSample: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
+    case kStSampleSelect: return (size_t)a.S * 4;
+    case kStBound: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
+    case kStScan: return a.rows ? (size_t)(a.N + 1) * 4 : 0;
+    case kStSelect: return (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8;
+    default: return (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
+  }
+}
+
+// The kernel of a stage for the variant of `a` (its width, scan mode, queries per lane).
+template <bool ONE, int M>
+const void* stage_kernel(const TopkArgs& a, int st) {
+  const int W32 = a.W32;
+  const bool lds_lut = a.N <= 16384;
+  const bool pow2 = (W32 & (W32 - 1)) == 0;
+  switch (st) {
+    case kStSample:
+#define BS_SAMPLE(w) \
+  return lds_lut ? (const void*)topk_sample_scores_kernel<ONE, M, w, true> : (const void*)topk_sample_scores_kernel<ONE, M, w, false>
       switch (W32) {
-        case 2: hipLaunchKernelGGL((topk_scan_kernel<2, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 4: hipLaunchKernelGGL((topk_scan_kernel<4, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 8: hipLaunchKernelGGL((topk_scan_kernel<8, 4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 16: hipLaunchKernelGGL((topk_scan_kernel<16, 2>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 32: hipLaunchKernelGGL((topk_scan_kernel<32, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 64: hipLaunchKernelGGL((topk_scan_kernel<64, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        default: hipLaunchKernelGGL((topk_scan_kernel<128, 1>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+        case 2: BS_SAMPLE(2);
+        case 4: BS_SAMPLE(4);
+        case 8: BS_SAMPLE(8);
+        case 16: BS_SAMPLE(16);
+        case 32: BS_SAMPLE(32);
+        case 64: BS_SAMPLE(64);
+        case 128: BS_SAMPLE(128);
+        default: BS_SAMPLE(0);
       }
-    } else {
-      int WC = 64;
-      while (W32 % WC) WC >>= 1;
-      switch (WC) {
-        case 2: hipLaunchKernelGGL((topk_scan_generic_kernel<2>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 4: hipLaunchKernelGGL((topk_scan_generic_kernel<4>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 8: hipLaunchKernelGGL((topk_scan_generic_kernel<8>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 16: hipLaunchKernelGGL((topk_scan_generic_kernel<16>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        case 32: hipLaunchKernelGGL((topk_scan_generic_kernel<32>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
-        default: hipLaunchKernelGGL((topk_scan_generic_kernel<64>), g, b, 0, s, a, n_slabs, slab, nqb4); break;
+#undef BS_SAMPLE
+    case kStSampleSelect: return (const void*)topk_sample_select_kernel<ONE, M>;
+    case kStBound: return lds_lut ? (const void*)topk_bound_kernel<ONE, M, true> : (const void*)topk_bound_kernel<ONE, M, false>;
+    case kStScan:
+      if (a.rows) {
+        switch (W32) {
+          case 2: return (const void*)topk_scan_rows_kernel<ONE, M, 2>;
+          case 4: return (const void*)topk_scan_rows_kernel<ONE, M, 4>;
+          case 8: return (const void*)topk_scan_rows_kernel<ONE, M, 8>;
+          case 16: return (const void*)topk_scan_rows_kernel<ONE, M, 16>;
+          case 32: return (const void*)topk_scan_rows_kernel<ONE, M, 32>;
+          case 64: return (const void*)topk_scan_rows_kernel<ONE, M, 64>;
+          default: return (const void*)topk_scan_rows_kernel<ONE, M, 128>;
+        }
       }
+      if (pow2 && W32 <= 128) {
+        const int q = (int)a.qpl;
+        switch (W32) {
+          case 2: return q == 4 ? (const void*)topk_scan_kernel<ONE, 2, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 2, 2> : (const void*)topk_scan_kernel<ONE, 2, 1>;
+          case 4: return q == 4 ? (const void*)topk_scan_kernel<ONE, 4, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 4, 2> : (const void*)topk_scan_kernel<ONE, 4, 1>;
+          case 8: return q == 4 ? (const void*)topk_scan_kernel<ONE, 8, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 8, 2> : (const void*)topk_scan_kernel<ONE, 8, 1>;
+          case 16: return q == 4 ? (const void*)topk_scan_kernel<ONE, 16, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 16, 2> : (const void*)topk_scan_kernel<ONE, 16, 1>;
+          case 32: return (const void*)topk_scan_kernel<ONE, 32, 1>;
+          case 64: return (const void*)topk_scan_kernel<ONE, 64, 1>;
+          default: return (const void*)topk_scan_kernel<ONE, 128, 1>;
+        }
+      } else {
+        int WC = 64;
+        while (W32 % WC) WC >>= 1;
+        switch (WC) {
+          case 2: return (const void*)topk_scan_generic_kernel<ONE, 2>;
+          case 4: return (const void*)topk_scan_generic_kernel<ONE, 4>;
+          case 8: return (const void*)topk_scan_generic_kernel<ONE, 8>;
+          case 16: return (const void*)topk_scan_generic_kernel<ONE, 16>;
+          case 32: return (const void*)topk_scan_generic_kernel<ONE, 32>;
+          default: return (const void*)topk_scan_generic_kernel<ONE, 64>;
+        }
+      }
+    case kStSelect: return a.rows ? (const void*)topk_select_kernel<ONE, M, false> : (const void*)topk_select_kernel<ONE, M, true>;
+    default: return (const void*)topk_fallback_kernel<ONE, M>;
+  }
+}
+
+const void* stage_kernel_m(bool one, int measure, const TopkArgs& a, int st) {
+  if (one) {
+    switch (measure) {
+      case BS_IP: return stage_kernel<true, BS_IP>(a, st);
+      case BS_HAMMING: return stage_kernel<true, BS_HAMMING>(a, st);
+      case BS_JACCARD: return stage_kernel<true, BS_JACCARD>(a, st);
+      default: return stage_kernel<true, BS_COSINE>(a, st);
     }
   }
-  // 3. select
-  {
-    const size_t lds = (size_t)a.kpad * 8 + (size_t)kSelectLdsKeys * 8;
-    ScopedTiming timing("topk_select", s);
-    if (p.rows)
-      hipLaunchKernelGGL((topk_select_kernel<M, false>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
-    else
-      hipLaunchKernelGGL((topk_select_kernel<M, true>), dim3((unsigned)a.nQ), dim3(kThreads), lds, s, a);
+  switch (measure) {
+    case BS_IP: return stage_kernel<false, BS_IP>(a, st);
+    case BS_HAMMING: return stage_kernel<false, BS_HAMMING>(a, st);
+    case BS_JACCARD: return stage_kernel<false, BS_JACCARD>(a, st);
+    default: return stage_kernel<false, BS_COSINE>(a, st);
   }
-  // 4. fallback for overflowed queries (exits at once when none overflowed)
-  if (p.S < a.nC) {
-    const size_t lds = (size_t)a.kpad * 8 + (size_t)W64 * 8;
-    ScopedTiming timing("topk_fallback", s);
-    hipLaunchKernelGGL((topk_fallback_kernel<M>), dim3((unsigned)p.F), dim3(kThreads), lds, s, a);
-  }
-  return launch_status();
+}
+
+bs_status launch_group_kernel(const void* fn, const GroupArgs& g, int64_t grid, size_t lds, hipStream_t s) {
+  if (grid < 1 || grid > INT32_MAX) return BS_ERR_ARG;
+  void* args[] = {const_cast<GroupArgs*>(&g)};
+  const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kThreads), args, lds, s);
+  return e == hipSuccess ? BS_OK : BS_ERR_HIP;
+}
+
+// Blocks of `fn` that fit one CU at `lds` bytes (at least 1).
+int64_t blocks_per_cu(const void* fn, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kThreads, lds) != hipSuccess || nb < 1) nb = 1;
+  return nb;
+}
+
+// Plan -> argument block. ws: the item's scratch; the LUT comes from the item.
+void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
+  a.Q = it.Q;
+  a.C = it.C;
+  a.t32 = it.t32;
+  a.popQ = it.popQ;
+  a.popC = it.popC;
+  a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
+  a.skeys = reinterpret_cast<uint32_t*>(ws + p.off_skeys);
+  a.qc = reinterpret_cast<QConst*>(ws + p.off_qc);
+  a.cnts = reinterpret_cast<int32_t*>(ws + p.off_cnts);
+  a.cands = reinterpret_cast<uint64_t*>(ws + p.off_cands);
+  a.scnt = reinterpret_cast<int32_t*>(ws + p.off_scnt);
+  a.slots = reinterpret_cast<uint64_t*>(ws + p.off_slots);
+  a.qovf = reinterpret_cast<int32_t*>(ws + p.off_qovf);
+  a.keys = reinterpret_cast<uint64_t*>(ws + p.off_keys);
+  a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
+  a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
+  a.out_idx = it.out_idx;
+  a.out_score = it.out_score;
+  a.nQ = it.nQ;
+  a.nQp = (it.nQ + 63) / 64 * 64;
+  a.nC = it.nC;
+  a.S = p.S;
+  a.stride = p.stride;
+  a.n_slabs = p.n_slabs;
+  a.slab = p.slab;
+  a.nqb4 = p.nqb4;
+  a.scap = p.scap;
+  a.kmax = p.kmax;
+  a.lds_keys = p.lds_keys;
+  a.s_rblocks = p.s_rblocks;
+  a.s_nqb = p.s_nqb;
+  a.s_qb = p.s_qb;
+  a.F = p.F;
+  a.N = it.N;
+  a.W32 = it.N / 32;
+  a.k = it.k;
+  int kpad = 1;
+  while (kpad < it.k) kpad <<= 1;
+  a.kpad = kpad;
+  a.qpl = (int32_t)p.qpl;
+  a.rows = p.rows ? 1 : 0;
 }
 
 }  // namespace
@@ -934,12 +1156,167 @@ bs_status run_topk(TopkArgs a, const Plan& p, hipStream_t s) {
 // Slot-count override for tests of the overflow path (negative = automatic).
 static int64_t g_scap_override = -1;
 
+// ---- group plans ----------------------------------------------------------------
+struct TopkGroup {
+  int32_t measure = 0;
+  bool persistent = true;
+  std::vector<TopkArgs> args;                   // per item (host copy)
+  std::vector<std::vector<int32_t>> classes;    // item indices per kernel-variant class
+  struct Launch {                               // one stage of one class
+    int32_t cls, st;
+    const void* fn;
+    GroupArgs g;
+    int64_t grid;
+    size_t lds;
+  };
+  std::vector<Launch> launches;                 // stage-major order
+};
+
+bs_status topk_item_check(const TopkItem& it, int32_t measure) {
+  if (it.nQ < 0 || it.nQ > INT32_MAX || it.nC < 1 || it.nC > INT32_MAX || !valid_width(it.N) || it.k < 1 ||
+      it.k > BS_MAX_K || it.k > it.nC || measure < 0 || measure > 3)
+    return BS_ERR_ARG;
+  if (!it.C || !it.popC || !it.t32 || ((!it.Q || !it.popQ || !it.out_idx) && it.nQ > 0)) return BS_ERR_NULL;
+  return BS_OK;
+}
+
+size_t topk_item_workspace(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tune) {
+  return make_plan(nQ, nC, N, k, tune).total;
+}
+
+size_t topk_group_meta_bytes(int32_t n_items) {
+  if (n_items < 0) return 0;
+  // argument blocks, then one offset table per (stage, class); at most one class per item
+  return align256((size_t)n_items * sizeof(TopkArgs)) +
+         (size_t)kStages * (size_t)n_items * align256(((size_t)n_items + 1) * sizeof(int64_t));
+}
+
+bs_status topk_group_create(const TopkItem* items, const TopkTune* tunes, int32_t n, int32_t measure,
+                            void* const* item_ws, void* meta, size_t meta_bytes, bool persistent,
+                            TopkGroup** out) {
+  if (!out) return BS_ERR_NULL;
+  *out = nullptr;
+  if (n < 0 || measure < 0 || measure > 3) return BS_ERR_ARG;
+  if (n > 0 && (!items || !item_ws || !meta)) return BS_ERR_NULL;
+  if (meta_bytes < topk_group_meta_bytes(n) || (reinterpret_cast<uintptr_t>(meta) & 255)) return BS_ERR_WORKSPACE;
+  for (int32_t i = 0; i < n; ++i) {
+    const bs_status st = topk_item_check(items[i], measure);
+    if (st != BS_OK) return st;
+    if (!item_ws[i] || (reinterpret_cast<uintptr_t>(item_ws[i]) & 255)) return BS_ERR_WORKSPACE;
+  }
+  std::unique_ptr<TopkGroup> G(new TopkGroup);
+  G->measure = measure;
+  G->persistent = persistent;
+  G->args.resize(n);
+  const TopkTune dflt;
+  for (int32_t i = 0; i < n; ++i) {
+    const Plan p = make_plan(items[i].nQ, items[i].nC, items[i].N, items[i].k, tunes ? tunes[i] : dflt);
+    fill_args(G->args[i], p, items[i], static_cast<char*>(item_ws[i]));
+  }
+  // classes: items that share every kernel variant (width, scan mode, queries per lane)
+  for (int32_t i = 0; i < n; ++i) {
+    if (G->args[i].nQ == 0) continue;
+    int32_t c = -1;
+    for (size_t j = 0; j < G->classes.size(); ++j) {
+      const TopkArgs& r = G->args[G->classes[j][0]];
+      if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.qpl == G->args[i].qpl) c = (int32_t)j;
+    }
+    if (c < 0) {
+      G->classes.emplace_back();
+      c = (int32_t)G->classes.size() - 1;
+    }
+    G->classes[c].push_back(i);
+  }
+  int lds_max = 0, n_cu = 0;
+  device_limits(&lds_max, &n_cu);
+  if (n_cu < 1) n_cu = 1;
+  // upload: argument blocks, then the offset tables
+  char* m = static_cast<char*>(meta);
+  const size_t args_bytes = align256((size_t)n * sizeof(TopkArgs));
+  const size_t tab_bytes = align256(((size_t)n + 1) * sizeof(int64_t));
+  std::vector<char> host(topk_group_meta_bytes(n), 0);
+  if (n > 0) memcpy(host.data(), G->args.data(), (size_t)n * sizeof(TopkArgs));
+  for (int st = 0; st < kStages; ++st) {
+    for (size_t c = 0; c < G->classes.size(); ++c) {
+      const std::vector<int32_t>& ci = G->classes[c];
+      // the class's items, in item order, as a contiguous sub-array of argument blocks is not
+      // guaranteed, so each class gets its own copy of the blocks after the offsets
+      const size_t at = args_bytes + ((size_t)st * n + c) * tab_bytes;
+      int64_t* off = reinterpret_cast<int64_t*>(host.data() + at);
+      int64_t total = 0;
+      size_t lds = 0;
+      for (size_t j = 0; j < ci.size(); ++j) {
+        off[j] = total;
+        total += stage_blocks(G->args[ci[j]], st);
+        const size_t l = stage_lds(G->args[ci[j]], st);
+        lds = l > lds ? l : lds;
+      }
+      off[ci.size()] = total;
+      if (total == 0) continue;
+      if (lds > (size_t)65536) return BS_ERR_ARG;  // never with the limits above
+      TopkGroup::Launch L;
+      L.cls = (int32_t)c;
+      L.st = st;
+      L.fn = stage_kernel_m(false, measure, G->args[ci[0]], st);
+      L.g.items = nullptr;
+      L.g.voff = reinterpret_cast<const int64_t*>(m + at);
+      L.g.total = total;
+      L.g.n = (int32_t)ci.size();
+      L.g.one = G->args[ci[0]];
+      L.lds = lds;
+      L.grid = total;
+      if (persistent) {
+        const int64_t cap = blocks_per_cu(L.fn, lds) * n_cu;
+        if (L.grid > cap) L.grid = cap;
+      }
+      G->launches.push_back(L);
+    }
+  }
+  // per-class argument blocks: the class's items packed in class order
+  // (stored in the first class-sized run of the argument region)
+  std::vector<TopkArgs> packed;
+  std::vector<size_t> class_base(G->classes.size());
+  for (size_t c = 0; c < G->classes.size(); ++c) {
+    class_base[c] = packed.size();
+    for (int32_t i : G->classes[c]) packed.push_back(G->args[i]);
+  }
+  if (!packed.empty()) memcpy(host.data(), packed.data(), packed.size() * sizeof(TopkArgs));
+  for (TopkGroup::Launch& L : G->launches)
+    L.g.items = reinterpret_cast<const TopkArgs*>(m) + class_base[L.cls];
+  if (!host.empty() && hipMemcpy(meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
+    return BS_ERR_HIP;
+  *out = G.release();
+  return BS_OK;
+}
+
+bs_status topk_group_launch(const TopkGroup* g, hipStream_t s, int32_t cls) {
+  if (!g) return BS_ERR_NULL;
+  for (const TopkGroup::Launch& L : g->launches) {
+    if (cls >= 0 && L.cls != cls) continue;
+    ScopedTiming timing(kStageTimer[L.st], s);
+    const bs_status st = launch_group_kernel(L.fn, L.g, L.grid, L.lds, s);
+    if (st != BS_OK) return st;
+  }
+  return BS_OK;
+}
+
+int32_t topk_group_classes(const TopkGroup* g) { return g ? (int32_t)g->classes.size() : 0; }
+
+int32_t topk_group_class_items(const TopkGroup* g, int32_t cls, int32_t* items, int32_t cap) {
+  if (!g || cls < 0 || cls >= (int32_t)g->classes.size()) return 0;
+  const std::vector<int32_t>& ci = g->classes[cls];
+  for (int32_t j = 0; j < (int32_t)ci.size() && j < cap; ++j) items[j] = ci[j];
+  return (int32_t)ci.size();
+}
+
+void topk_group_destroy(TopkGroup* g) { delete g; }
+
 }  // namespace bs
 
 extern "C" size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   using namespace bs;
   if (nQ < 0 || nC < 1 || !valid_width(N) || k < 1 || k > BS_MAX_K || k > nC) return 0;
-  return make_plan(nQ, nC, N, k).total;
+  return make_plan(nQ, nC, N, k, TopkTune()).total;
 }
 
 extern "C" int bs_debug_set_topk_slab_capacity(int64_t cap) {
@@ -957,7 +1334,7 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
     return BS_ERR_ARG;
   if (!C || ((!Q || !out_idx) && nQ > 0)) return BS_ERR_NULL;
   if (nQ > INT32_MAX) return BS_ERR_ARG;
-  Plan p = make_plan(nQ, nC, N, k);
+  Plan p = make_plan(nQ, nC, N, k, TopkTune());
   if (!workspace || workspace_bytes < p.total || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return BS_ERR_WORKSPACE;
   bs_status st = check_device();
@@ -968,41 +1345,20 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
     p.kmax = p.S + p.n_slabs * p.scap;
   }
   char* ws = static_cast<char*>(workspace);
+  TopkItem it;
+  it.Q = Q;
+  it.popQ = popQ ? popQ : reinterpret_cast<const int32_t*>(ws + p.off_popq);
+  it.nQ = nQ;
+  it.C = C;
+  it.popC = popC ? popC : reinterpret_cast<const int32_t*>(ws + p.off_popc);
+  it.nC = nC;
+  it.N = N;
+  it.k = k;
+  it.out_idx = out_idx;
+  it.out_score = out_score;
+  it.t32 = reinterpret_cast<const float*>(ws + p.off_t32);
   TopkArgs a;
-  a.Q = Q;
-  a.C = C;
-  a.t32 = reinterpret_cast<const float*>(ws + p.off_t32);
-  a.popQ = popQ ? popQ : reinterpret_cast<const int32_t*>(ws + p.off_popq);
-  a.popC = popC ? popC : reinterpret_cast<const int32_t*>(ws + p.off_popc);
-  a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
-  a.skeys = reinterpret_cast<uint32_t*>(ws + p.off_skeys);
-  a.qc = reinterpret_cast<QConst*>(ws + p.off_qc);
-  a.cnts = reinterpret_cast<int32_t*>(ws + p.off_cnts);
-  a.cands = reinterpret_cast<uint64_t*>(ws + p.off_cands);
-  a.scnt = reinterpret_cast<int32_t*>(ws + p.off_scnt);
-  a.slots = reinterpret_cast<uint64_t*>(ws + p.off_slots);
-  a.qovf = reinterpret_cast<int32_t*>(ws + p.off_qovf);
-  a.keys = reinterpret_cast<uint64_t*>(ws + p.off_keys);
-  a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
-  a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
-  a.out_idx = out_idx;
-  a.out_score = out_score;
-  a.nQ = nQ;
-  a.nQp = (nQ + 63) / 64 * 64;
-  a.nC = nC;
-  a.S = p.S;
-  a.stride = p.stride;
-  a.n_slabs = p.n_slabs;
-  a.slab = p.slab;
-  a.nqb4 = p.nqb4;
-  a.scap = p.scap;
-  a.kmax = p.kmax;
-  a.N = N;
-  a.W32 = N / 32;
-  a.k = k;
-  int kpad = 1;
-  while (kpad < k) kpad <<= 1;
-  a.kpad = kpad;
+  fill_args(a, p, it, ws);
   hipStream_t s = as_stream(stream);
   {
     ScopedTiming timing("topk_prep", s);
@@ -1012,14 +1368,19 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   }
   st = launch_status();
   if (st != BS_OK) return st;
-  switch (measure) {
-    case BS_IP:
-      return run_topk<BS_IP>(a, p, s);
-    case BS_HAMMING:
-      return run_topk<BS_HAMMING>(a, p, s);
-    case BS_JACCARD:
-      return run_topk<BS_JACCARD>(a, p, s);
-    default:
-      return run_topk<BS_COSINE>(a, p, s);
+  // one item: arguments inline, one hardware block per virtual block
+  for (int stg = 0; stg < kStages; ++stg) {
+    const int64_t total = stage_blocks(a, stg);
+    if (total == 0) continue;
+    GroupArgs g;
+    g.items = nullptr;
+    g.voff = nullptr;
+    g.total = total;
+    g.n = 1;
+    g.one = a;
+    ScopedTiming timing(kStageTimer[stg], s);
+    st = launch_group_kernel(stage_kernel_m(true, measure, a, stg), g, total, stage_lds(a, stg), s);
+    if (st != BS_OK) return st;
   }
+  return BS_OK;
 }

@@ -96,3 +96,43 @@ def test_topk_rejects_bad_arguments(lib):
     assert t(FAKE, None, 10, FAKE, None, 100, 256, 2, 5, FAKE, None, FAKE, need - 1, None) == 3
     assert lib.bs_topk_workspace_size(10, 100, 256, 101) == 0
     assert lib.bs_topk_workspace_size(10, 100, 100, 5) == 0
+
+
+def _batch_item(**kw):
+    from paper_1910_04658_amd.binding import BatchItem
+    it = BatchItem()
+    it.indptr = it.indices = it.q_indptr = it.q_indices = it.pi = 0x1000
+    it.sketches = it.popcounts = it.q_sketches = it.q_popcounts = it.out_idx = it.out_score = 0x1000
+    it.n_rows, it.nnz, it.n_queries, it.q_nnz, it.d, it.N, it.k = 100, 500, 10, 50, 1000, 256, 10
+    for k, v in kw.items():
+        setattr(it, k, v)
+    return it
+
+
+def test_batch_rejects_bad_arguments(lib):
+    from paper_1910_04658_amd.binding import BatchItem
+    good = _batch_item()
+    arr = (BatchItem * 1)(good)
+    assert lib.bs_batch_workspace_size(arr, 1) > 0
+    assert lib.bs_batch_workspace_size(arr, 0) == 0
+    for bad in [dict(N=100), dict(k=101), dict(k=0), dict(n_rows=0), dict(d=0), dict(nnz=-1), dict(n_queries=-1),
+                dict(N=131072)]:
+        assert lib.bs_batch_workspace_size((BatchItem * 1)(_batch_item(**bad)), 1) == 0, bad
+    h = P()
+    c = lib.bs_batch_create
+    assert c(arr, 1, 2, None, 0, None, 0, None, None) == 1          # no handle out-pointer
+    assert c(arr, 0, 2, None, 0, FAKE, 1 << 30, None, ctypes.byref(h)) == 2
+    assert c(arr, 1, 7, None, 0, FAKE, 1 << 30, None, ctypes.byref(h)) == 2
+    assert c((BatchItem * 1)(_batch_item(pi=0)), 1, 2, None, 0, FAKE, 1 << 30, None, ctypes.byref(h)) == 1
+    assert c((BatchItem * 1)(_batch_item(out_idx=0)), 1, 2, None, 0, FAKE, 1 << 30, None, ctypes.byref(h)) == 1
+    # no queries: the query pointers may be NULL
+    assert lib.bs_batch_workspace_size((BatchItem * 1)(_batch_item(n_queries=0, q_nnz=0, q_indptr=0, q_indices=0,
+                                                                   q_sketches=0, out_idx=0)), 1) > 0
+    assert c(arr, 1, 2, None, 0, None, 0, None, ctypes.byref(h)) == 3   # no workspace
+    assert c(arr, 1, 2, None, 0, FAKE, 16, None, ctypes.byref(h)) == 3  # too small
+    assert lib.bs_batch_run(None, None) == 1
+    assert lib.bs_batch_run_eager(None, None) == 1
+    assert lib.bs_batch_autotune(None, 1, None) == 1
+    assert lib.bs_batch_shapes(None, None, 0) == 0
+    assert lib.bs_batch_graph_nodes(None) == 0
+    lib.bs_batch_destroy(None)
