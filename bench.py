@@ -317,6 +317,69 @@ def serving_eval(dev, n_corpus=10_000_000, d=1_000_000, N=2048, k=50, n_req=4000
             "online": online, "offline_all_at_once": offline}
 
 
+def batch_eval(dev, n_problems=64, k=100, reps=5, check=4):
+    """64 independent problems (sizes 1k-200k rows, d 1e4-1e6, mean row
+    weight 20-2,000, N in {128, 512, 2048, 8192}, queries 1% of the rows, at
+    least 100; top-100 Jaccard) sketched and ranked by one graph launch after
+    autotuning, against the same problems run one after another through
+    bs_sketch and bs_topk."""
+    import torch
+
+    import datagen
+    from paper_1910_04658_amd import binding as bs
+    t = time.time()
+    specs = datagen.batch_specs(n_problems)
+    probs = datagen.device_batch(specs, dev, k=k)
+    torch.cuda.synchronize()
+    t_gen = time.time() - t
+    rows = sum(sp.n + sp.nq for sp in specs)
+    pairs = sum(sp.n * sp.nq for sp in specs)
+    nnz = sum(p["indices"].numel() + p["q_indices"].numel() for p in probs)
+    b = bs.Batch(probs, "js")
+    t = time.time()
+    b.autotune(reps=2)
+    torch.cuda.synchronize()
+    t_tune = time.time() - t
+    b.run()  # records the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+
+    def one_by_one():
+        outs = []
+        for p in probs:
+            C, pC = bs.sketch(p["indptr"], p["indices"], p["pi"], p["N"])
+            Q, pQ = bs.sketch(p["q_indptr"], p["q_indices"], p["pi"], p["N"])
+            ws = bs._workspace(bs.topk_workspace_size(Q.shape[0], C.shape[0], p["N"], p["k"]), dev)
+            outs.append((C, ws, bs.topk(Q, C, p["N"], "js", p["k"], popQ=pQ, popC=pC, workspace=ws)))
+        return outs
+    single = one_by_one()  # warm-up, and the reference results
+    torch.cuda.synchronize()
+    same = all(torch.equal(b.out[i]["idx"], single[i][2][0]) and torch.equal(b.out[i]["sketches"], single[i][0])
+               for i in range(min(check, len(probs))))
+    del single
+    e0.record()
+    for _ in range(2):
+        one_by_one()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / 2
+    out = {"problems": n_problems, "rows_sketched": rows, "nnz": nnz, "pair_estimates": pairs,
+           "widths": sorted({sp.N for sp in specs}), "k": k, "measure": "jaccard",
+           "graph_ms": ms_graph, "graph_nodes": b.graph_nodes(),
+           "vectors_per_s": rows / (ms_graph * 1e-3), "pair_estimates_per_s": pairs / (ms_graph * 1e-3),
+           "one_by_one_ms": ms_single, "speedup_vs_one_by_one": ms_single / ms_graph,
+           "same_as_one_by_one": bool(same), "autotune_s": t_tune, "shapes": b.shapes(),
+           "input_gen_s": t_gen, "workspace_GB": b.workspace.numel() / 1e9}
+    b.close()
+    return out
+
+
 def cpu_baseline(corpus, queries, pi, N, k, nq):
     """The CPU oracle (plain C, OpenMP over rows) on a bounded sample."""
     import numpy as np
@@ -354,6 +417,7 @@ def main():
     ap.add_argument("--no-mse", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-estimator evaluation")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
@@ -458,6 +522,10 @@ def main():
                                  "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
     if not args.no_mse:
         out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.no_batch:
+        log("batched problems ...")
+        out["batching"] = batch_eval(dev)
+        log("batching: %s" % out["batching"])
     if not args.no_serving:
         log("serving run ...")
         out["serving"] = serving_eval(dev)

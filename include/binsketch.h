@@ -313,14 +313,16 @@ void bs_timing_reset(void);
 int bs_timing_get(const char* name, double* total_ms, int64_t* count);
 
 /*
- * Testing hook, not for production callers: caps the candidate slots that
- * bs_topk keeps per (query, corpus slab) at `cap` (0 sends every query with a
- * candidate outside the sample to the whole-corpus fallback; a negative value
- * restores the automatic size) so that tests can drive the overflow path,
- * which must return the same result. Process-wide; not thread-safe. Always
- * returns 0.
+ * Testing hook, not for production callers: bs_topk keeps at most
+ * `slab_capacity` candidate slots per (query, corpus slab) (0 sends every
+ * query with a candidate outside the sample to the whole-corpus fallback)
+ * and selects at most `lds_keys` candidates in LDS (larger sets are
+ * compacted and selected in place in the workspace). Negative values
+ * restore the automatic sizes. Lets tests drive the overflow and in-place
+ * paths, which must return the same result. Process-wide; not thread-safe.
+ * Returns 0.
  */
-int bs_debug_set_topk_slab_capacity(int64_t cap);
+int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys);
 
 #ifdef __cplusplus
 }

@@ -103,8 +103,8 @@ def load():
             L.bs_mlp_train_step.restype = ctypes.c_int
             L.bs_mlp_to_bf16.argtypes = [p, p, p]
             L.bs_mlp_to_bf16.restype = ctypes.c_int
-            L.bs_debug_set_topk_slab_capacity.argtypes = [i64]
-            L.bs_debug_set_topk_slab_capacity.restype = ctypes.c_int
+            L.bs_debug_set_topk_limits.argtypes = [i64, i64]
+            L.bs_debug_set_topk_limits.restype = ctypes.c_int
             BI, BSh = ctypes.POINTER(BatchItem), ctypes.POINTER(BatchShape)
             L.bs_batch_workspace_size.argtypes = [BI, i32]
             L.bs_batch_workspace_size.restype = sz
@@ -304,8 +304,10 @@ def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool
     return out_idx, out_score
 
 
-def debug_set_topk_slab_capacity(cap: int):
-    load().bs_debug_set_topk_slab_capacity(int(cap))
+def debug_set_topk_limits(slab_capacity: int = -1, lds_keys: int = -1):
+    """Test hook: shrink the top-k candidate slots per slab / the LDS key
+    buffer of the select (-1 = automatic)."""
+    load().bs_debug_set_topk_limits(int(slab_capacity), int(lds_keys))
 
 
 def timing_enable(on: bool = True):

@@ -42,7 +42,7 @@ std::vector<TopkTune> candidate_tunes(int32_t N) {
   const int W32 = N / 32;
   const bool small = (W32 & (W32 - 1)) == 0 && W32 <= 16;
   const int qpls[3] = {1, 2, 4};
-  const int waves[4] = {4096, 8192, 16384, 32768};
+  const int waves[3] = {4096, 8192, 16384};
   for (int q : qpls) {
     if (q > 1 && !small) continue;
     for (int w : waves) {

@@ -67,7 +67,7 @@ struct Plan {
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
   int64_t lds_keys;                                   // select: candidate keys held in LDS
-  size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_slots, off_qovf, off_keys,
+  size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_qovf,
       off_scratch, off_mtab, off_ovf, off_skeys, total;
 };
 
@@ -151,14 +151,13 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.off_popc = take((size_t)nC * 4);
   p.off_qc = take(nQs * sizeof(QConst));
   p.off_cnts = take(nQs * 4);
-  p.off_cands = take(nQs * (size_t)p.S * 8);
+  p.off_cands = take(nQs * (size_t)p.kmax * 8);  // per query: S sample slots, then n_slabs x scap
   p.off_scnt = take(nQs * (size_t)p.n_slabs * 4);
-  p.off_slots = take(nQs * (size_t)p.n_slabs * (size_t)p.scap * 8);
   p.off_qovf = take(nQs * 4);
-  p.off_keys = take(nQs * (size_t)p.kmax * 8);
+
   p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
   p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
-  p.off_ovf = take((nQs + 1) * 4);
+  p.off_ovf = take((nQs + 2) * 4);
   p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
   return p;
@@ -264,14 +263,14 @@ struct TopkArgs {
   const int32_t* __restrict__ popC;
   QConst* __restrict__ qc;
   int32_t* __restrict__ cnts;      // [nQ] sample candidates per query
-  uint64_t* __restrict__ cands;    // [nQ][S] sample candidates (x_ab << 32 | row)
+  uint64_t* __restrict__ cands;    // [nQ][kmax]: S sample candidates (keys), then n_slabs x scap scan
+                                   // candidates (keys from the row-lane scan, x_ab << 32 | row from the
+                                   // query-lane scan); compacted in place into keys by the select
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
-  uint64_t* __restrict__ slots;    // [nQ][n_slabs][scap] scan candidates
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
-  uint64_t* __restrict__ keys;     // [nQ][kmax] compacted keys (large candidate sets)
   uint64_t* __restrict__ scratch;  // [F][nC]
   uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
-  int32_t* __restrict__ ovf;       // [1 + nQ]: count, then the overflowed queries
+  int32_t* __restrict__ ovf;       // [2 + nQ]: count, key buffers taken, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
   float* __restrict__ out_score;   // [nQ][k] or null
@@ -297,9 +296,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.cnts = c->cnts;
   a.cands = c->cands;
   a.scnt = c->scnt;
-  a.slots = c->slots;
   a.qovf = c->qovf;
-  a.keys = c->keys;
   a.scratch = c->scratch;
   a.mtab = c->mtab;
   a.ovf = c->ovf;
@@ -440,10 +437,13 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
   const uint32_t* src = a.skeys + (size_t)q * a.S;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) keys[i] = src[i];
   if (threadIdx.x == 0) nsel = 0;
-  if (q == 0 && threadIdx.x == 0) a.ovf[0] = 0;
+  if (q == 0 && threadIdx.x == 0) {
+    a.ovf[0] = 0;
+    a.ovf[1] = 0;
+  }
   __syncthreads();
   const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed);
-  uint64_t* cq = a.cands + (size_t)q * a.S;
+  uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     if (keys[i] >= tau_key) {
       const uint32_t slot = atomicAdd(&nsel, 1u);
@@ -546,7 +546,7 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
   for (int j = 0; j < QPL; ++j) {
     cnt[j] = 0;
-    dst[j] = a.slots + ((size_t)(q_ok[j] ? q[j] : 0) * a.n_slabs + sl) * a.scap;
+    dst[j] = a.cands + (size_t)(q_ok[j] ? q[j] : 0) * a.kmax + a.S + sl * a.scap;
   }
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row
   const int64_t s_end = a.S * a.stride;
@@ -634,7 +634,7 @@ __device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid
   const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C);
   const uint16_t* mt = a.mtab + q;
   int cnt = 0;
-  uint64_t* dst = a.slots + ((size_t)(q_ok ? q : 0) * a.n_slabs + sl) * a.scap;
+  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + sl * a.scap;
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;
   const int64_t s_end = a.S * a.stride;
   for (int64_t c = c_begin; c < c_end; ++c) {
@@ -745,7 +745,7 @@ __device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
           if (slot < a.scap) {
             const float sc = score_f32<M>(lut[popQ[q]], Tc, Tu);
-            a.slots[((size_t)q * a.n_slabs + sl) * a.scap + slot] = make_key<M>(sc, (uint32_t)rr);
+            a.cands[(size_t)q * a.kmax + a.S + sl * a.scap + slot] = make_key<M>(sc, (uint32_t)rr);
           }
         }
         if (lane == q) cntv += __popcll(bal);
@@ -807,8 +807,8 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   __shared__ uint32_t nsel;
   __shared__ uint32_t total_s;
   constexpr int PER = kSelChunk / kThreads;
-  if (a.qovf[q]) {  // block-uniform  // a slab overflowed its slots: hand the query to the fallback kernel
-    if (threadIdx.x == 0) a.ovf[1 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+  if (a.qovf[q]) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
+    if (threadIdx.x == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
     return;
   }
   const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
@@ -821,16 +821,19 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   const int64_t ns = a.cnts[q];
   const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  uint64_t* keys = n <= a.lds_keys ? sm + a.kpad : a.keys + (size_t)q * a.kmax;
+  uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then n_slabs x scap slab slots
+  // Large candidate sets are compacted in place: entry j's destination is
+  // never after its source (a slab's count never exceeds its capacity, the
+  // sample's never exceeds S), so with every source of one step of 256 read
+  // before any destination of that step is written, nothing unread is
+  // overwritten. Small sets go to LDS.
+  const bool in_lds = n <= a.lds_keys;
+  uint64_t* keys = in_lds ? sm + a.kpad : region;
   const int32_t xq = a.popQ[q];
   const float Tq = a.t32[xq];
-  // 2. compact: the sample's candidates, then every slab's slots in slab order.
-  // Per chunk of slabs, an exclusive scan of the counts goes to LDS and every
-  // thread takes output positions j, t + 256, ..., finding the slab of j by
-  // binary search, so that no thread walks a long slab alone.
-  const uint64_t* cs = a.cands + (size_t)q * a.S;
-  for (int64_t i = threadIdx.x; i < ns; i += kThreads) keys[i] = cs[i];
-  const uint64_t* slots = a.slots + (size_t)q * a.n_slabs * a.scap;
+  if (in_lds)
+    for (int64_t i = threadIdx.x; i < ns; i += kThreads) keys[i] = region[i];
+  const uint64_t* slots = region + a.S;
   int64_t base = ns;
   for (int64_t c0 = 0; c0 < a.n_slabs; c0 += kSelChunk) {
     uint32_t cnt[PER], sum = 0;
@@ -850,15 +853,23 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     if (threadIdx.x == kThreads - 1) off[kSelChunk] = incl;
     __syncthreads();
     const uint32_t T = off[kSelChunk];
-    for (uint32_t j = threadIdx.x; j < T; j += kThreads) {
-      int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= j) lo = mid;
-        else hi = mid - 1;
+    // every thread takes output positions j = t, t + 256, ... and finds the
+    // slab of j by binary search, so no thread walks a long slab alone
+    for (uint32_t j0 = 0; j0 < T; j0 += kThreads) {
+      const uint32_t j = j0 + threadIdx.x;
+      uint64_t v = 0;
+      if (j < T) {
+        int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (off[mid] <= j) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint64_t e = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
+        v = RAW ? cand_key<M>(e, xq, Tq, a) : e;
       }
-      const uint64_t e = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
-      keys[base + j] = RAW ? cand_key<M>(e, xq, Tq, a) : e;
+      if (!in_lds) __syncthreads();  // block-uniform
+      if (j < T) keys[base + j] = v;
     }
     base += T;
     __syncthreads();
@@ -881,7 +892,7 @@ __device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int6
   uint64_t* keys = a.scratch + (size_t)b * a.nC;
   const int32_t n_ovf = a.ovf[0];
   for (int64_t i = b; i < n_ovf; i += nb) {
-    const int64_t q = a.ovf[1 + i];
+    const int64_t q = a.ovf[2 + i];
     const uint64_t* qrow = a.Q + (size_t)q * W64;
     for (int w = threadIdx.x; w < W64; w += kThreads) qw[w] = qrow[w];
     const int32_t xq = a.popQ[q];
@@ -1119,9 +1130,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.cnts = reinterpret_cast<int32_t*>(ws + p.off_cnts);
   a.cands = reinterpret_cast<uint64_t*>(ws + p.off_cands);
   a.scnt = reinterpret_cast<int32_t*>(ws + p.off_scnt);
-  a.slots = reinterpret_cast<uint64_t*>(ws + p.off_slots);
   a.qovf = reinterpret_cast<int32_t*>(ws + p.off_qovf);
-  a.keys = reinterpret_cast<uint64_t*>(ws + p.off_keys);
   a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
   a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
   a.out_idx = it.out_idx;
@@ -1153,8 +1162,9 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
 
 }  // namespace
 
-// Slot-count override for tests of the overflow path (negative = automatic).
+// Overrides for tests of the overflow paths (negative = automatic).
 static int64_t g_scap_override = -1;
+static int64_t g_ldskeys_override = -1;
 
 // ---- group plans ----------------------------------------------------------------
 struct TopkGroup {
@@ -1319,8 +1329,9 @@ extern "C" size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int3
   return make_plan(nQ, nC, N, k, TopkTune()).total;
 }
 
-extern "C" int bs_debug_set_topk_slab_capacity(int64_t cap) {
-  bs::g_scap_override = cap < 0 ? -1 : cap;
+extern "C" int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys) {
+  bs::g_scap_override = slab_capacity < 0 ? -1 : slab_capacity;
+  bs::g_ldskeys_override = lds_keys < 0 ? -1 : lds_keys;
   return 0;
 }
 
@@ -1344,6 +1355,7 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
     p.scap = g_scap_override;
     p.kmax = p.S + p.n_slabs * p.scap;
   }
+  if (g_ldskeys_override >= 0 && g_ldskeys_override < p.lds_keys) p.lds_keys = g_ldskeys_override;
   char* ws = static_cast<char*>(workspace);
   TopkItem it;
   it.Q = Q;
