@@ -51,6 +51,8 @@ constexpr int kSelChunk = 1024;      // slabs compacted per step of the select k
 constexpr int kScanWaves = 16384;    // waves of the scan grid, about
 constexpr int kRowWaves = 4096;      // waves of the row-lane scan (small batches)
 constexpr int kRowsMaxQ = 64;        // largest batch of the row-lane scan
+constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the word-split scan
+constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFallbackBlocks = 16;
 
 struct QConst {  // per-query constants written by the sample pass
@@ -66,6 +68,7 @@ struct Plan {
   int64_t qpl, ngrp, nqb4, n_slabs, slab, scap, kmax;  // scan geometry
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
+  bool split;                                         // word-split scan (wide sketches)
   int64_t lds_keys;                                   // select: candidate keys held in LDS
   size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_qovf,
       off_scratch, off_mtab, off_ovf, off_skeys, total;
@@ -93,8 +96,19 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // corpus rows on the lanes instead, each wave over a run of 64-row tiles.
   const bool rows_ok = nQ <= kRowsMaxQ && pow2 && W32 <= 128;
   p.rows = rows_ok && tune.rows != 0;
-  if (p.rows) p.qpl = 1;
-  if (p.rows) {
+  // Sketches of 256 or 512 words do not fit one lane's registers: four waves
+  // share a 64-query group, each holding a quarter of the words.
+  p.split = !p.rows && pow2 && (W32 == 256 || W32 == 512);
+  if (p.rows || p.split) p.qpl = 1;
+  if (p.split) {
+    p.ngrp = nqb;
+    p.nqb4 = nqb;  // one block per (row slab, query group)
+    const int64_t waves = tune.waves > 0 ? tune.waves : kScanWaves;
+    int64_t rslabs = p.ngrp > 0 ? (waves + kSplitWaves * p.ngrp - 1) / (kSplitWaves * p.ngrp) : 1;
+    if (rslabs > nC) rslabs = nC;
+    if (rslabs < 1) rslabs = 1;
+    p.slab = (nC + rslabs - 1) / rslabs;
+  } else if (p.rows) {
     const int64_t waves = tune.waves > 0 ? tune.waves : kRowWaves;
     const int64_t tiles = (nC + kWave - 1) / kWave;
     const int64_t tpw = (tiles + waves - 1) / waves;
@@ -107,20 +121,24 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
     p.slab = (nC + n_slabs - 1) / n_slabs;
   }
   p.n_slabs = (nC + p.slab - 1) / p.slab;
-  // candidate slots per (query, slab): the expected count e = slab * k / S
+  // candidate slots per (query, slab): the expected count e = rows * k / S
   // (the threshold is the k-th best of S sampled rows) plus six standard
   // deviations and a margin for ties at the threshold, so that overflow into
   // the fallback path is rare
-  const double e = p.S > 0 ? (double)p.slab * k / (double)p.S : 0.0;
+  // (a slot slab of the word-split scan is one wave's quarter of a row slab)
+  const int64_t slot_rows = p.split ? (p.slab + kSplitWaves - 1) / kSplitWaves : p.slab;
+  if (p.split) p.n_slabs *= kSplitWaves;
+  const double e = p.S > 0 ? (double)slot_rows * k / (double)p.S : 0.0;
   int64_t scap = (int64_t)ceil(2.0 * e + 6.0 * sqrt(e)) + 8;
-  p.scap = scap < p.slab ? scap : p.slab;
+  p.scap = scap < slot_rows ? scap : slot_rows;
   if (p.S >= nC) {  // the sample covers the corpus: no scan, no slabs
     p.n_slabs = 0;
     p.scap = 0;
   }
   p.kmax = p.S + p.n_slabs * p.scap;
-  // sample-score grid: 256-row blocks x query blocks, ~2k blocks in all
-  p.s_rblocks = (p.S + kThreads - 1) / kThreads;
+  // sample-score grid: 256-row blocks (64 for the word-split pass) x query
+  // blocks, ~2k blocks in all
+  p.s_rblocks = p.split ? (p.S + kWave - 1) / kWave : (p.S + kThreads - 1) / kThreads;
   p.s_nqb = (2048 + p.s_rblocks - 1) / p.s_rblocks;
   if (p.s_nqb > nQ) p.s_nqb = nQ;
   if (p.s_nqb < 1) p.s_nqb = 1;
@@ -278,7 +296,7 @@ struct TopkArgs {
   int64_t s_rblocks, s_nqb, s_qb;  // sample-score grid: row blocks x query blocks of s_qb queries
   int64_t F;                       // fallback blocks
   int32_t N, W32, k, kpad;
-  int32_t qpl, rows;               // scan variant: queries per lane, row-lane scan
+  int32_t qpl, rows, split;        // scan variant: queries per lane, row-lane scan, word-split scan
 };
 
 // Member-wise copy through the constant address space, so that the fields of
@@ -324,6 +342,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.kpad = c->kpad;
   a.qpl = c->qpl;
   a.rows = c->rows;
+  a.split = c->split;
   return a;
 }
 
@@ -421,6 +440,62 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
     if (i_ok) {
       a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
     }
+  }
+}
+
+// 1a'. The same for sketches of 256 or 512 words: a block of four waves
+// takes 64 sample rows; wave w holds words [w*WS, (w+1)*WS) of its lane's
+// row, counts that quarter against each query (scalar), and the partial
+// counts meet in LDS every kSplitRows queries.
+template <int M, int WS>
+__device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx, int64_t by) {
+  extern __shared__ float lut[];  // T[0..N] (N <= 16384)
+  __shared__ uint32_t part[kSplitRows][kSplitWaves][kWave];
+  for (int x = threadIdx.x; x <= a.N; x += kThreads) lut[x] = a.t32[x];
+  __syncthreads();
+  constexpr int PS = 32;
+  constexpr int P = WS / PS;
+  const int lane = threadIdx.x % kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t W32 = kSplitWaves * WS;
+  const int64_t i = bx * kWave + lane;  // sample index
+  const bool i_ok = i < a.S;
+  const int64_t row = (i_ok ? i : a.S - 1) * a.stride;
+  uint32_t rw[WS];
+  {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.C) + (size_t)row * W32 + wid * WS;
+#pragma unroll
+    for (int w = 0; w < WS; ++w) rw[w] = src[w];
+  }
+  const int32_t xc = a.popC[row];
+  const float Tc = lut[xc];
+  const int64_t q_begin = by * a.s_qb;
+  const int64_t q_end = q_begin + a.s_qb < a.nQ ? q_begin + a.s_qb : a.nQ;
+  const uint32_t* Q32 = reinterpret_cast<const uint32_t*>(a.Q) + wid * WS;
+  for (int64_t q0 = q_begin; q0 < q_end; q0 += kSplitRows) {
+    for (int r = 0; r < kSplitRows; ++r) {
+      const int64_t q = q0 + r < q_end ? q0 + r : q_end - 1;
+      uint32_t acc = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const cptr<uint32_t> qw = as_const(Q32 + (size_t)q * W32 + p * PS);
+#pragma unroll
+        for (int w = 0; w < PS; ++w) acc = bcnt_add(qw[w] & rw[p * PS + w], acc);
+      }
+      part[r][wid][lane] = acc;
+    }
+    __syncthreads();
+    for (int r = wid; r < kSplitRows; r += kSplitWaves) {
+      const int64_t q = q0 + r;
+      if (q >= q_end) break;  // wave-uniform
+      int32_t x = 0;
+#pragma unroll
+      for (int w = 0; w < kSplitWaves; ++w) x += (int32_t)part[r][w][lane];
+      const int32_t xq = as_const(a.popQ)[q];
+      const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - x]);
+      if (i_ok) a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
+    }
+    __syncthreads();
   }
 }
 
@@ -659,6 +734,79 @@ __device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid
   }
   if (q_ok) {
     a.scnt[(size_t)q * a.n_slabs + sl] = cnt < a.scap ? cnt : (int32_t)a.scap;
+    if (cnt > a.scap) a.qovf[q] = 1;
+  }
+}
+
+// Word-split scan for sketches of 256 or 512 words: a block of four waves
+// takes one 64-query group and one row slab. Wave w holds words
+// [w*WS, (w+1)*WS) of its lane's query and counts that quarter of every row
+// (rows on the scalar unit, as above); every kSplitRows rows the partial
+// counts meet in LDS and wave w finishes rows w, w+4, ... of the step (sum,
+// threshold test, survivor slot in its own quarter of the slab's slots).
+template <int WS>
+__device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) {
+  __shared__ uint32_t part[kSplitRows][kSplitWaves][kWave];
+  constexpr int PS = 32;  // words per scalar piece
+  constexpr int P = WS / PS;
+  const int lane = threadIdx.x % kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int64_t ngrp = a.nqb4;
+  const int64_t rs = bid / ngrp;  // row slab
+  const int64_t g = bid % ngrp;   // query group
+  const int64_t c_begin = rs * a.slab;
+  const int64_t c_end = c_begin + a.slab < a.nC ? c_begin + a.slab : a.nC;
+  // every virtual block has rows and queries: all waves reach every barrier
+  const int64_t W32 = kSplitWaves * WS;
+  const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C) + wid * WS;
+  const cptr<int32_t> popC = as_const(a.popC);
+  const int64_t q = g * kWave + lane;
+  const bool q_ok = q < a.nQ;
+  uint32_t qw[WS];
+  {
+    const uint32_t* qrow = reinterpret_cast<const uint32_t*>(a.Q) + (size_t)(q_ok ? q : a.nQ - 1) * W32 + wid * WS;
+#pragma unroll
+    for (int w = 0; w < WS; ++w) qw[w] = qrow[w];
+  }
+  const int64_t ss = rs * kSplitWaves + wid;  // this wave's slot slab
+  int cnt = 0;
+  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + ss * a.scap;
+  const uint16_t* mt = a.mtab + q;  // q < nQp
+  int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row at or after the rows seen
+  const int64_t s_end = a.S * a.stride;
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += kSplitRows) {
+#pragma unroll 2
+    for (int r = 0; r < kSplitRows; ++r) {
+      const int64_t c = c0 + r < c_end ? c0 + r : c_end - 1;  // rows past the end are not finished
+      uint32_t acc = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const cptr<uint32_t> cw = as_const(C32 + (size_t)c * W32 + p * PS);
+#pragma unroll
+        for (int w = 0; w < PS; ++w) acc = bcnt_add(cw[w] & qw[p * PS + w], acc);
+      }
+      part[r][wid][lane] = acc;
+    }
+    __syncthreads();
+    for (int r = wid; r < kSplitRows; r += kSplitWaves) {
+      const int64_t c = c0 + r;
+      if (c >= c_end) break;  // wave-uniform
+      uint32_t x = 0;
+#pragma unroll
+      for (int w = 0; w < kSplitWaves; ++w) x += part[r][w][lane];
+      while (next_s < c) next_s += a.stride;
+      const bool in_sample = c == next_s && c < s_end;
+      const int32_t xc = popC[c];
+      const uint16_t m = mt[(size_t)xc * a.nQp];
+      if (q_ok && !in_sample && x >= (uint32_t)m) {
+        if (cnt < a.scap) dst[cnt] = ((uint64_t)x << 32) | (uint32_t)c;
+        ++cnt;
+      }
+    }
+    __syncthreads();
+  }
+  if (q_ok) {
+    a.scnt[(size_t)q * a.n_slabs + ss] = cnt < a.scap ? cnt : (int32_t)a.scap;
     if (cnt > a.scap) a.qovf[q] = 1;
   }
 }
@@ -961,6 +1109,10 @@ template <bool ONE, int M, int W32T, bool LDS_LUT>
 __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(GroupArgs g) {
   BS_GROUP_LOOP((sample_scores_body<M, W32T, LDS_LUT>(a, lb % a.s_rblocks, lb / a.s_rblocks)))
 }
+template <bool ONE, int M, int WS>
+__global__ __launch_bounds__(kThreads) void topk_sample_split_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((sample_split_body<M, WS>(a, lb % a.s_rblocks, lb / a.s_rblocks)))
+}
 template <bool ONE, int M>
 __global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(GroupArgs g) {
   BS_GROUP_LOOP((sample_select_body<M>(a, lb)))
@@ -976,6 +1128,10 @@ __global__ __launch_bounds__(kThreads) void topk_scan_kernel(GroupArgs g) {
 template <bool ONE, int WC>
 __global__ __launch_bounds__(kThreads) void topk_scan_generic_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_generic_body<WC>(a, lb)))
+}
+template <bool ONE, int WS>
+__global__ __launch_bounds__(kThreads) void topk_scan_split_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((scan_split_body<WS>(a, lb)))
 }
 template <bool ONE, int M, int W32T>
 __global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(GroupArgs g) {
@@ -1002,9 +1158,11 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
     case kStSample: return a.s_rblocks * a.s_nqb;
     case kStSampleSelect: return a.nQ;
     case kStBound: return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 1 + kBoundX - 1) / kBoundX) : 0;
-    case kStScan: return scan ? (a.rows ? (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave)
-                                        : a.n_slabs * a.nqb4)
-                              : 0;
+    case kStScan:
+      if (!scan) return 0;
+      if (a.rows) return (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave);
+      if (a.split) return (a.n_slabs / kSplitWaves) * a.nqb4;
+      return a.n_slabs * a.nqb4;
     case kStSelect: return a.nQ;
     default: return scan ? a.F : 0;
   }
@@ -1014,7 +1172,7 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
 size_t stage_lds(const TopkArgs& a, int st) {
   const bool lds_lut = a.N <= 16384;
   switch (st) {
-    case kStSample: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
+    case kStSample: return (lds_lut || a.split) ? (size_t)(a.N + 1) * 4 : 0;
     case kStSampleSelect: return (size_t)a.S * 4;
     case kStBound: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
     case kStScan: return a.rows ? (size_t)(a.N + 1) * 4 : 0;
@@ -1031,6 +1189,9 @@ const void* stage_kernel(const TopkArgs& a, int st) {
   const bool pow2 = (W32 & (W32 - 1)) == 0;
   switch (st) {
     case kStSample:
+      if (a.split)
+        return W32 == 256 ? (const void*)topk_sample_split_kernel<ONE, M, 64>
+                          : (const void*)topk_sample_split_kernel<ONE, M, 128>;
 #define BS_SAMPLE(w) \
   return lds_lut ? (const void*)topk_sample_scores_kernel<ONE, M, w, true> : (const void*)topk_sample_scores_kernel<ONE, M, w, false>
       switch (W32) {
@@ -1058,6 +1219,7 @@ const void* stage_kernel(const TopkArgs& a, int st) {
           default: return (const void*)topk_scan_rows_kernel<ONE, M, 128>;
         }
       }
+      if (a.split) return W32 == 256 ? (const void*)topk_scan_split_kernel<ONE, 64> : (const void*)topk_scan_split_kernel<ONE, 128>;
       if (pow2 && W32 <= 128) {
         const int q = (int)a.qpl;
         switch (W32) {
@@ -1158,6 +1320,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.kpad = kpad;
   a.qpl = (int32_t)p.qpl;
   a.rows = p.rows ? 1 : 0;
+  a.split = p.split ? 1 : 0;
 }
 
 }  // namespace

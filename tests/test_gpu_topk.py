@@ -53,11 +53,12 @@ def test_scan_path(m, N, k, dev):
 
 
 @pytest.mark.parametrize("m", MEASURES)
-@pytest.mark.parametrize("N,nq", [(256, 130), (320, 70), (1024, 65), (8192, 20)])
+@pytest.mark.parametrize("N,nq", [(256, 130), (320, 70), (1024, 65), (8192, 20), (8192, 130), (16384, 33)])
 def test_scan_path_query_lanes(m, N, nq, dev):
     """Batches above 64 queries (and widths the row-lane scan does not take:
-    N = 320 is not a power-of-two word count, N = 8192 exceeds 128 words) go
-    through the query-lane scan; ragged query counts."""
+    N = 320 is not a power-of-two word count; N = 8192 and 16384 exceed 128
+    words and take the word-split scan) go through the query-lane scans;
+    ragged query counts."""
     c = _mid("c20011", lambda: datagen.lognormal_corpus(20011, d=30000, seed=22))
     w, S = sketch_both(c, N, 6, dev)
     q = np.linspace(0, 20010, nq).astype(np.int64)
