@@ -3,8 +3,9 @@
 // own corpus, queries, map pi, dimension d and sketch width N.
 //
 // The whole batch is one HIP graph. Its nodes are grouped kernels, each
-// covering every problem in the batch: a flag-clearing kernel, ONE sketch
-// launch for every corpus and query matrix, one LUT launch per distinct width,
+// covering every problem in the batch: a flag-clearing kernel, one launch
+// that packs every map to 16-bit targets, ONE sketch launch for every corpus
+// and query matrix, one LUT launch per distinct width,
 // then the top-k stages (sample, threshold table, scan, select, fallback),
 // one launch per stage and kernel variant (a variant is fixed by the width and
 // the scan tile shape). The grids are persistent (at most what fits the
@@ -81,6 +82,7 @@ bs_status check_item(const bs_batch_item& it) {
 struct Layout {
   std::vector<int32_t> widths;     // distinct N, ascending
   std::vector<size_t> lut_off;     // per distinct N
+  std::vector<size_t> map_off;     // per item: its map as 16-bit targets
   size_t sketch_meta, topk_meta;   // offsets
   std::vector<size_t> item_off;    // per item top-k scratch
   size_t total;
@@ -95,6 +97,10 @@ Layout make_layout(const bs_batch_item* items, int32_t n) {
   for (int32_t N : L.widths) {
     L.lut_off.push_back(o);
     o += align256((size_t)(N + 1) * 4);
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    L.map_off.push_back(o);
+    o += align256((size_t)items[i].d * 2);
   }
   L.sketch_meta = o;
   o += align256(sketch_group_meta_bytes(2 * n));
@@ -248,13 +254,15 @@ extern "C" bs_status bs_batch_create(const bs_batch_item* items, int32_t n_items
   for (int32_t i = 0; i < n_items; ++i) {
     const bs_batch_item& x = items[i];
     sk.push_back(SketchItem{x.indptr, x.indices, x.n_rows, x.nnz, x.pi, x.d, x.N, x.sketches, x.popcounts,
-                            err_flags ? err_flags + i : nullptr});
+                            err_flags ? err_flags + i : nullptr,
+                            reinterpret_cast<uint16_t*>(b->ws + L.map_off[i])});
   }
   for (int32_t i = 0; i < n_items; ++i) {
     const bs_batch_item& x = items[i];
     if (x.n_queries == 0) continue;
     sk.push_back(SketchItem{x.q_indptr, x.q_indices, x.n_queries, x.q_nnz, x.pi, x.d, x.N, x.q_sketches,
-                            x.q_popcounts, err_flags ? err_flags + i : nullptr});
+                            x.q_popcounts, err_flags ? err_flags + i : nullptr,
+                            reinterpret_cast<uint16_t*>(b->ws + L.map_off[i])});
   }
   st = sketch_group_create(sk.data(), (int32_t)sk.size(), b->ws + L.sketch_meta, sketch_group_meta_bytes(2 * n_items),
                            true, &b->sk);

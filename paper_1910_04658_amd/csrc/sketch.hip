@@ -41,6 +41,7 @@ struct SketchArgs {
   const int32_t* __restrict__ indptr;
   const int32_t* __restrict__ indices;
   const int32_t* __restrict__ pi;
+  const uint16_t* __restrict__ pi16;  // the map as 16-bit targets (validated), or null
   uint32_t* __restrict__ out32;  // [n_rows][W32]
   int32_t* __restrict__ pop;     // [n_rows] or null
   int32_t* __restrict__ err;     // [1] or null
@@ -99,7 +100,7 @@ __device__ __forceinline__ void sketch_window(const SketchArgs& a, int64_t wave,
         const bool live = k < e1;
         in[u] = live && (uint32_t)idx[u] < d32;
         if (live && !in[u]) errbits |= BS_FLAG_INDEX;
-        j[u] = in[u] ? a.pi[idx[u]] : 0;
+        j[u] = in[u] ? (a.pi16 ? (int32_t)a.pi16[idx[u]] : a.pi[idx[u]]) : 0;
       }
       int rowv[kUnroll];
 #pragma unroll
@@ -165,6 +166,7 @@ __device__ __forceinline__ SketchArgs load_sketch_args(const SketchArgs* p) {
   a.indptr = c->indptr;
   a.indices = c->indices;
   a.pi = c->pi;
+  a.pi16 = c->pi16;
   a.out32 = c->out32;
   a.pop = c->pop;
   a.err = c->err;
@@ -176,6 +178,68 @@ __device__ __forceinline__ SketchArgs load_sketch_args(const SketchArgs* p) {
   a.G = c->G;
   a.stride = c->stride;
   return a;
+}
+
+// The maps of a group as 16-bit targets (N <= 65536): half the bytes of
+// the 32-bit table, so a 10^6-entry map (2 MB) stays in L2 while the grid
+// works through its problem. Values outside [0, N) are reported (BS_FLAG_MAP,
+// as when the map is packed for LDS) and stored as 0. Virtual blocks of 1024
+// entries, four per thread.
+struct PackItem {
+  const int32_t* pi;
+  uint16_t* out;
+  int64_t d;
+  int32_t N;
+  int32_t* err;
+};
+
+__global__ __launch_bounds__(256) void pack16_group_kernel(const PackItem* items, const int64_t* boff, int32_t n,
+                                                         int64_t total) {
+  const cptr<int64_t> off = as_const(boff);
+  for (int64_t vb = blockIdx.x; vb < total; vb += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= vb) lo = mid;
+      else hi = mid - 1;
+    }
+    const cptr<PackItem> it = as_const(items + lo);
+    const int32_t* pi = it->pi;
+    uint16_t* out = it->out;
+    const int64_t d = it->d;
+    const uint32_t N = (uint32_t)it->N;
+    int32_t* err = it->err;
+    const int64_t e0 = ((vb - off[lo]) * 256 + threadIdx.x) * 4;
+    if (e0 >= d) continue;
+    uint32_t v[4];
+    if (e0 + 4 <= d && (reinterpret_cast<uintptr_t>(pi) & 15) == 0) {
+      const int4 q = *reinterpret_cast<const int4*>(pi + e0);
+      v[0] = (uint32_t)q.x;
+      v[1] = (uint32_t)q.y;
+      v[2] = (uint32_t)q.z;
+      v[3] = (uint32_t)q.w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = e0 + u < d ? (uint32_t)pi[e0 + u] : 0u;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (v[u] >= N) {
+        bad = true;
+        v[u] = 0;
+      }
+    }
+    if (bad && err) atomicOr(err, (int32_t)BS_FLAG_MAP);
+    if (e0 + 4 <= d && (reinterpret_cast<uintptr_t>(out) & 7) == 0) {
+      const uint64_t w = (uint64_t)v[0] | ((uint64_t)v[1] << 16) | ((uint64_t)v[2] << 32) | ((uint64_t)v[3] << 48);
+      *reinterpret_cast<uint64_t*>(out + e0) = w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + u < d) out[e0 + u] = (uint16_t)v[u];
+    }
+  }
 }
 
 __global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_group_kernel(const SketchArgs* items,
@@ -408,11 +472,17 @@ struct SketchGroup {
   int64_t total = 0;
   int32_t wave_words = 0;
   int64_t grid = 0;
+  const PackItem* packs = nullptr;  // maps to pack to 16 bits first
+  const int64_t* poff = nullptr;
+  int32_t n_packs = 0;
+  int64_t pack_blocks = 0;
+  int64_t pack_grid = 0;
 };
 
 size_t sketch_group_meta_bytes(int32_t n) {
   if (n < 0) return 0;
-  return align256((size_t)n * sizeof(SketchArgs)) + align256(((size_t)n + 1) * sizeof(int64_t));
+  return align256((size_t)n * sizeof(SketchArgs)) + align256(((size_t)n + 1) * sizeof(int64_t)) +
+         align256((size_t)n * sizeof(PackItem)) + align256(((size_t)n + 1) * sizeof(int64_t));
 }
 
 bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, size_t meta_bytes, bool persistent,
@@ -424,6 +494,8 @@ bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, si
   if (meta_bytes < sketch_group_meta_bytes(n) || (reinterpret_cast<uintptr_t>(meta) & 255)) return BS_ERR_WORKSPACE;
   std::vector<SketchArgs> args(n);
   std::vector<int64_t> woff((size_t)n + 1);
+  std::vector<PackItem> packs;
+  std::vector<int64_t> poff(1, 0);
   int64_t total = 0;
   int32_t wave_words = 1;
   for (int32_t i = 0; i < n; ++i) {
@@ -433,6 +505,15 @@ bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, si
     a.indptr = items[i].indptr;
     a.indices = items[i].indices;
     a.pi = items[i].pi;
+    a.pi16 = items[i].pi16;
+    if (items[i].pi16) {  // each packed map once (items may share one)
+      bool seen = false;
+      for (const PackItem& pk : packs) seen = seen || pk.out == items[i].pi16;
+      if (!seen) {
+        packs.push_back(PackItem{items[i].pi, items[i].pi16, items[i].d, items[i].N, items[i].err});
+        poff.push_back(poff.back() + (items[i].d + 1023) / 1024);
+      }
+    }
     a.out32 = reinterpret_cast<uint32_t*>(items[i].sketches);
     a.pop = items[i].popcounts;
     a.err = items[i].err;
@@ -453,12 +534,20 @@ bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, si
   char* m = static_cast<char*>(meta);
   std::vector<char> host(sketch_group_meta_bytes(n), 0);
   const size_t args_bytes = align256((size_t)n * sizeof(SketchArgs));
+  const size_t woff_bytes = align256(((size_t)n + 1) * sizeof(int64_t));
+  const size_t packs_bytes = align256((size_t)n * sizeof(PackItem));
   if (n > 0) memcpy(host.data(), args.data(), (size_t)n * sizeof(SketchArgs));
   memcpy(host.data() + args_bytes, woff.data(), woff.size() * sizeof(int64_t));
+  if (!packs.empty()) memcpy(host.data() + args_bytes + woff_bytes, packs.data(), packs.size() * sizeof(PackItem));
+  memcpy(host.data() + args_bytes + woff_bytes + packs_bytes, poff.data(), poff.size() * sizeof(int64_t));
   if (!host.empty() && hipMemcpy(meta, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess)
     return BS_ERR_HIP;
   g->items = reinterpret_cast<const SketchArgs*>(m);
   g->woff = reinterpret_cast<const int64_t*>(m + args_bytes);
+  g->packs = reinterpret_cast<const PackItem*>(m + args_bytes + woff_bytes);
+  g->poff = reinterpret_cast<const int64_t*>(m + args_bytes + woff_bytes + packs_bytes);
+  g->n_packs = (int32_t)packs.size();
+  g->pack_blocks = poff.back();
   g->n = n;
   g->total = total;
   g->wave_words = wave_words;
@@ -475,6 +564,13 @@ bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, si
     const int64_t cap = (int64_t)nb * (n_cu > 0 ? n_cu : 1);
     if (g->grid > cap) g->grid = cap;
   }
+  g->pack_grid = g->pack_blocks;
+  if (persistent) {
+    int lds_max = 0, n_cu = 0;
+    device_limits(&lds_max, &n_cu);
+    const int64_t cap = (int64_t)8 * (n_cu > 0 ? n_cu : 1);
+    if (g->pack_grid > cap) g->pack_grid = cap;
+  }
   *out = g.release();
   return BS_OK;
 }
@@ -482,7 +578,12 @@ bs_status sketch_group_create(const SketchItem* items, int32_t n, void* meta, si
 bs_status sketch_group_launch(const SketchGroup* g, hipStream_t s) {
   if (!g) return BS_ERR_NULL;
   if (g->total == 0) return BS_OK;
-  if (g->grid > INT32_MAX) return BS_ERR_ARG;
+  if (g->grid > INT32_MAX || g->pack_grid > INT32_MAX) return BS_ERR_ARG;
+  if (g->pack_blocks > 0) {
+    ScopedTiming timing("sketch_pack16", s);
+    hipLaunchKernelGGL(pack16_group_kernel, dim3((unsigned)g->pack_grid), dim3(256), 0, s, g->packs, g->poff,
+                       g->n_packs, g->pack_blocks);
+  }
   ScopedTiming timing("sketch_group", s);
   hipLaunchKernelGGL(sketch_group_kernel, dim3((unsigned)g->grid), dim3(kWavesPerBlock * kWave),
                      (size_t)kWavesPerBlock * g->wave_words * 4, s, g->items, g->woff, g->n, g->total,
@@ -529,6 +630,7 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
     L.s.indptr = indptr;
     L.s.indices = indices;
     L.s.pi = pi;
+    L.s.pi16 = nullptr;
     L.s.out32 = reinterpret_cast<uint32_t*>(sketches);
     L.s.pop = popcounts;
     L.s.err = err_flag;
@@ -568,6 +670,7 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
   a.indptr = indptr;
   a.indices = indices;
   a.pi = pi;
+  a.pi16 = nullptr;
   a.out32 = reinterpret_cast<uint32_t*>(sketches);
   a.pop = popcounts;
   a.err = err_flag;

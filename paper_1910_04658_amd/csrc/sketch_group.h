@@ -21,6 +21,7 @@ struct SketchItem {
   uint64_t* sketches;      // [n_rows][N/64]
   int32_t* popcounts;      // [n_rows] or null
   int32_t* err;            // error flag word or null
+  uint16_t* pi16;          // scratch for the map as 16-bit targets ([d], packed by the launch), or null
 };
 
 // Validates an item (the bs_sketch argument rules).
