@@ -24,6 +24,7 @@
 #include <string.h>
 
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "bs_common.h"
@@ -272,6 +273,15 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_group_kernel(co
 constexpr int kBigBlockWaves = 16;
 constexpr int kUnrollLds = 16;  // element loads in flight per lane
 
+// LDS byte addresses as plain integers, so that an address is one
+// shift-and-add from an index (the LDS base of the dynamic allocation is a
+// link-time constant the compiler cannot fold into the offset).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
+  return (uint32_t)(uintptr_t)(const lds_u32*)p;
+}
+__device__ __forceinline__ lds_u32* lds_ptr(uint32_t a) { return (lds_u32*)(uintptr_t)a; }
+
 struct SketchLdsArgs {
   SketchArgs s;
   const uint32_t* __restrict__ packed;  // bit-packed map (table_words - 1 words)
@@ -335,14 +345,32 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   uint32_t* stage_base = lds + A.table_words;
   const uint32_t emask = (1u << bits) - 1u;
 
-  // 1. copy the packed map (built by pack_map_kernel) into LDS, 16 bytes per
-  //    load, then clear the pad word read past the last entry.
   uint32_t errbits = 0;
+  // The packed map (built by pack_map_kernel) goes to LDS 16 bytes per load,
+  // every load of a thread in flight at once (one round trip for up to
+  // 128 KB); then the pad word read past the last entry is cleared.
   {
+    constexpr int CB = 8;
     const int n16 = (A.table_words - 1) / 4;  // whole 16-byte chunks of the packed words
     const uint4* src = reinterpret_cast<const uint4*>(A.packed);
     uint4* dst = reinterpret_cast<uint4*>(table);
-    for (int t = threadIdx.x; t < n16; t += blockDim.x) dst[t] = src[t];
+    for (int t0 = threadIdx.x; t0 < n16; t0 += (int)blockDim.x * CB) {
+      uint32_t v[CB][4];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int t = t0 + c * (int)blockDim.x;
+        const uint4 q = src[t < n16 ? t : 0];
+        v[c][0] = q.x;
+        v[c][1] = q.y;
+        v[c][2] = q.z;
+        v[c][3] = q.w;
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int t = t0 + c * (int)blockDim.x;
+        if (t < n16) dst[t] = make_uint4(v[c][0], v[c][1], v[c][2], v[c][3]);
+      }
+    }
     for (int t = n16 * 4 + threadIdx.x; t < A.table_words - 1; t += blockDim.x) table[t] = A.packed[t];
     if (threadIdx.x == 0) table[A.table_words - 1] = 0u;
   }
@@ -355,17 +383,82 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   uint32_t* sk = stage_base + (size_t)wid * a.stride;
   uint32_t* cnt = sk + (size_t)a.G * W32;
   const uint32_t d32 = (uint32_t)a.d;
+  // Rows split by set bits, not by count: wave w takes the rows that start
+  // in [w*nnz/W, (w+1)*nnz/W) of the element stream (W waves), found by a
+  // 32-ary search of indptr (lanes 0-31 for the start, 32-63 for the end).
+  // With a monotone indptr the ranges partition the rows; a range whose end
+  // comes before its start can only come from a malformed indptr and is
+  // reported.
   const int64_t total_waves = (int64_t)gridDim.x * kBigBlockWaves;
-  const int64_t per_wave = (a.n_rows + total_waves - 1) / total_waves;
   const int64_t wv = (int64_t)blockIdx.x * kBigBlockWaves + wid;
-  const int64_t rw0 = wv * per_wave;
-  const int64_t rw1 = rw0 + per_wave < a.n_rows ? rw0 + per_wave : a.n_rows;
+  int64_t rw0, rw1;
+  {
+    const int half = lane >> 5, hl = lane & 31;
+    const int64_t T = (wv + half) * a.nnz / total_waves;  // < 2^52: no overflow
+    int64_t lo = 0, hi = a.n_rows;  // the first row r with indptr[r] >= T lies in [lo, hi]
+    if (wv + half == 0) hi = 0;
+    if (wv + half >= total_waves) lo = a.n_rows;
+    while (__ballot(hi > lo) != 0) {  // at most five rounds: the interval shrinks 32-fold
+      const int64_t step = hi > lo ? (hi - lo + 31) / 32 : 1;
+      const int64_t pos = lo + hl * step;
+      const bool probe = pos < hi;
+      const int32_t v = probe ? a.indptr[pos] : 0;
+      const uint64_t m = __ballot(probe && (int64_t)v < T);
+      const int k = __popc(half ? (uint32_t)(m >> 32) : (uint32_t)m);  // probes below T
+      if (hi > lo) {
+        if (k == 0) {
+          hi = lo;
+        } else {
+          const int64_t nlo = lo + (k - 1) * step + 1, nhi = lo + k * step;
+          lo = nlo;
+          hi = nhi < hi ? nhi : hi;
+        }
+      }
+    }
+    const uint32_t lo_l = (uint32_t)lo, lo_h = (uint32_t)((uint64_t)lo >> 32);
+    rw0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo_h, 0) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane(lo_l, 0));
+    rw1 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(lo_h, 32) << 32) |
+                    (uint32_t)__builtin_amdgcn_readlane(lo_l, 32));
+  }
+  uint32_t range_err = rw1 < rw0 ? (uint32_t)BS_FLAG_INDPTR : 0u;
+  if (rw1 < rw0) rw1 = rw0;
 
   int32_t p_next = 0;
   if (rw0 < rw1) {
     const int g0 = (int)(rw1 - rw0 < a.G ? rw1 - rw0 : a.G);
     p_next = (lane <= g0) ? a.indptr[rw0 + lane] : 0;
   }
+  // The wave's elements are one contiguous run (its rows are consecutive), so
+  // the index stream is software-pipelined across windows: while a chunk of
+  // 1,024 indices is processed, the next chunk's loads are in flight.
+  // Prefetch positions are clamped into [0, nnz), so a malformed indptr can
+  // only waste a prefetch, never read out of bounds; a chunk whose start
+  // differs from the prefetched one reloads.
+  const int64_t nnz = a.nnz;
+  const int64_t wave_end = rw0 < rw1 ? (int64_t)a.indptr[rw1] : 0;  // prefetch bound only
+  uint32_t nidx[kUnrollLds];
+  int64_t pf_base = -1;
+  auto prefetch = [&](int64_t b) {
+    pf_base = b;
+    if (b >= 0 && b + (int64_t)kWave * kUnrollLds <= nnz) {
+      const int32_t* src = a.indices + b + lane;
+#pragma unroll
+      for (int u = 0; u < kUnrollLds; ++u) nidx[u] = (uint32_t)__builtin_nontemporal_load(src + u * kWave);
+    } else {  // positions fit 32 bits: nnz <= 2^31 - 1
+      const uint32_t ub = b < 0 ? 0u : (uint32_t)b, last = (uint32_t)(nnz - 1);
+#pragma unroll
+      for (int u = 0; u < kUnrollLds; ++u) {
+        const uint32_t pos = ub + (uint32_t)(u * kWave + lane);
+        nidx[u] = (uint32_t)__builtin_nontemporal_load(a.indices + (pos < last ? pos : last));
+      }
+    }
+  };
+  if (rw0 < rw1 && nnz > 0) prefetch((int64_t)__builtin_amdgcn_readfirstlane(p_next));
+  const uint32_t row_bytes = (uint32_t)W32 * 4u;
+  const uint32_t sk_b = lds_addr(sk), table_b = lds_addr(table);
+  const uint32_t dmax = d32 - 1u;
+  uint64_t badmask = 0;  // lanes that met an index outside [0, d)
   for (int64_t r0 = rw0; r0 < rw1; r0 += a.G) {
     const int g = (int)(rw1 - r0 < a.G ? rw1 - r0 : a.G);
     const int32_t p = p_next;
@@ -390,36 +483,73 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
       int cur = 0;
       int64_t nxt = (g > 1) ? (int64_t)__builtin_amdgcn_readlane(p, 1) : INT64_MAX;
       for (int64_t base = e0; base < e1; base += (int64_t)kWave * kUnrollLds) {
-        int32_t idx[kUnrollLds];
+        // Element u of lane l sits at base + u*64 + l. A full chunk has no
+        // per-element branches; the last chunk of a window skips its empty
+        // 64-element slices with a uniform branch and masks the lanes past
+        // the end of the partial one. An index outside [0, d) is flagged and
+        // clamped (the output is then undefined) so the table read stays
+        // inside LDS.
+        if (pf_base != base) prefetch(base);
+        uint32_t idx[kUnrollLds];
 #pragma unroll
-        for (int u = 0; u < kUnrollLds; ++u) {
-          const int64_t k = base + u * kWave + lane;
-          idx[u] = (k < e1) ? __builtin_nontemporal_load(a.indices + k) : -1;
+        for (int u = 0; u < kUnrollLds; ++u) idx[u] = nidx[u];
+        {
+          const int64_t next = base + (int64_t)kWave * kUnrollLds < e1 ? base + (int64_t)kWave * kUnrollLds : e1;
+          if (next < wave_end) prefetch(next);
+          else pf_base = -1;
         }
-        int rowv[kUnrollLds];
+        auto chunk = [&](auto full_tag) {
+          constexpr bool FULL = decltype(full_tag)::value;
+          const int rem = FULL ? kWave * kUnrollLds : (int)(e1 - base);
+          // LDS byte address of the stage row of slice u's elements: every
+          // 64-element slice starts at a uniform row; a row start inside the
+          // slice moves the lanes past it one row on (rows are longer than a
+          // slice on average, so this is about one compare per row start).
+          // Slices are taken in order, just before their ORs.
+          auto slice_rows = [&](int u) {
+            uint32_t ro = sk_b + (uint32_t)cur * row_bytes;
+            const int64_t s0 = base + u * kWave;
+            while (nxt < s0 + kWave) {  // wave-uniform
+              ro += (lane >= (int)(nxt - s0)) ? row_bytes : 0u;
+              ++cur;
+              nxt = (cur + 1 < g) ? (int64_t)__builtin_amdgcn_readlane(p, cur + 1) : INT64_MAX;
+            }
+            return ro;
+          };
+          // table word pairs, half a chunk at a time: addresses, then 16 reads
+          // in flight, then use (half keeps the registers within budget while
+          // the next chunk's loads are outstanding)
+          constexpr int H = kUnrollLds / 2;
 #pragma unroll
-        for (int u = 0; u < kUnrollLds; ++u) rowv[u] = cur;
-        const int64_t end = base + (int64_t)kWave * kUnrollLds;
-        while (nxt < end) {
+          for (int h = 0; h < 2; ++h) {
+            if (!FULL && h * H * kWave >= rem) break;  // wave-uniform: the rest is past the end
+            uint32_t bp[H], lo[H], hi[H];
 #pragma unroll
-          for (int u = 0; u < kUnrollLds; ++u) rowv[u] += (base + u * kWave + lane >= nxt) ? 1 : 0;
-          ++cur;
-          nxt = (cur + 1 < g) ? (int64_t)__builtin_amdgcn_readlane(p, cur + 1) : INT64_MAX;
-        }
+            for (int v = 0; v < H; ++v) {
+              const int u = h * H + v;
+              badmask |= __ballot((FULL || u * kWave + lane < rem) && idx[u] > dmax);
+              bp[v] = __umul24(idx[u] < dmax ? idx[u] : dmax, (uint32_t)bits);
+            }
 #pragma unroll
-        for (int u = 0; u < kUnrollLds; ++u) {
-          const int64_t k = base + u * kWave + lane;
-          if (k < e1) {
-            if ((uint32_t)idx[u] < d32) {
-              const uint32_t bp = (uint32_t)idx[u] * (uint32_t)bits;
-              const uint32_t lo = table[bp >> 5], hi = table[(bp >> 5) + 1];
-              const uint32_t j = __builtin_amdgcn_alignbit(hi, lo, bp & 31) & emask;
-              atomicOr(&sk[rowv[u] * W32 + (j >> 5)], 1u << (j & 31));
-            } else {
-              errbits |= BS_FLAG_INDEX;
+            for (int v = 0; v < H; ++v) {
+              const lds_u32* tw = lds_ptr(table_b + (__builtin_amdgcn_ubfe(bp[v], 5, 27) << 2));
+              lo[v] = tw[0];
+              hi[v] = tw[1];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int v = 0; v < H; ++v) {
+              const int u = h * H + v;
+              if (!FULL && u * kWave >= rem) break;  // wave-uniform
+              const uint32_t ro = slice_rows(u);
+              const uint32_t jj = __builtin_amdgcn_alignbit(hi[v], lo[v], bp[v]) & emask;
+              const uint32_t addr = ro + (__builtin_amdgcn_ubfe(jj, 5, 27) << 2);
+              if (FULL || u * kWave + lane < rem) __atomic_fetch_or(lds_ptr(addr), 1u << (jj & 31), __ATOMIC_RELAXED);
             }
           }
-        }
+        };
+        if (base + (int64_t)kWave * kUnrollLds <= e1) chunk(std::true_type());
+        else chunk(std::false_type());
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -438,6 +568,8 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (a.pop && lane < g) a.pop[r0 + lane] = (int32_t)cnt[lane];
   }
+  if (badmask) errbits |= BS_FLAG_INDEX;
+  errbits |= range_err;
   if (a.err && errbits) atomicOr(a.err, (int32_t)errbits);
 }
 
@@ -646,8 +778,8 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
     L.table_words = (int32_t)table_words;
     L.n_windows = (n_rows + Gl - 1) / Gl;
     const size_t lds = (size_t)table_bytes + (size_t)kBigBlockWaves * L.s.stride * 4;
-    // one block per CU; fewer when there are fewer than ~2 windows per wave
-    int64_t grid = (L.n_windows + 2 * kBigBlockWaves - 1) / (2 * kBigBlockWaves);
+    // one block per CU; fewer when there is less than one window per wave
+    int64_t grid = (L.n_windows + kBigBlockWaves - 1) / kBigBlockWaves;
     if (grid > n_cu) grid = n_cu;
     if (grid < 1) grid = 1;
     if ((size_t)lds <= (size_t)lds_max) {
