@@ -9,10 +9,11 @@ One step = the whole hot path over one batch of synthetic input:
      keep the top 100 per query (FP32 scores).
 at sketch width N = 1024 (also reported: N = 256 and N = 4096).
 
-Inputs are resident in device memory before timing starts. The timed region
-is exactly `--steps` steps between two device synchronisations. Per-kernel
-launch durations come from HIP events that the library records on the
-launching stream while timing is enabled.
+Inputs are resident in device memory before timing starts. The timed
+region is exactly `--steps` steps between two device synchronisations
+(`--graph`: replays of the step recorded into a HIP graph). Per-kernel launch
+durations come from a separate eager pass, from HIP events that the library
+records on the launching stream while timing is enabled.
 
 Printed: one JSON line (see the keys below). `value` is pair estimates per
 second of the whole step (sketching included).
@@ -167,21 +168,39 @@ class Step:
                 out_score=self.score, popQ=self.popQ, popC=self.popC)
 
 
-def timed(step, steps, warmup):
+def timed(step, steps, warmup, graph=False):
+    """ms per step and per-kernel mean launch times.
+
+    Eager launches by default; graph=True records the step's launches (two
+    sketches and the top-k stages) once into a HIP graph and times replays.
+    Kernel times come from a separate eager pass with the library's HIP-event
+    timing on (events inside the timed region would add to it)."""
     import torch
     bs = step.bs
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    bs.timing_collect()
-    bs.timing_reset()
-    bs.timing_enable(True)
+    run = step
+    if graph:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        run = g.replay
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        step()
+        run()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # per-kernel timing, eager
+    bs.timing_collect()
+    bs.timing_reset()
+    bs.timing_enable(True)
+    for _ in range(min(steps, 20)):
+        step()
+    torch.cuda.synchronize()
     bs.timing_enable(False)
     bad = bs.timing_collect()
     kt = {}
@@ -418,6 +437,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-estimator evaluation")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
+    ap.add_argument("--graph", action="store_true", help="time replays of the step recorded into a HIP graph")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
@@ -456,7 +476,7 @@ def main():
     for i, N in enumerate(widths):
         step = Step(dev_in, N, k, nC, nQ, dev)
         steps = args.steps if i == 0 else max(10, args.steps // 4)
-        ms, kt = timed(step, steps, args.warmup)
+        ms, kt = timed(step, steps, args.warmup, graph=args.graph)
         results[N] = (step, ms, kt, steps)
         log("N=%d: %.4f ms/step; kernels %s" % (N, ms, {n: round(v["avg_ms"], 4) for n, v in kt.items()}))
 

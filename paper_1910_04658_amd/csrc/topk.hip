@@ -69,6 +69,7 @@ struct Plan {
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
   bool split;                                         // word-split scan (wide sketches)
+  bool sel_lut;                                       // select keeps T in LDS
   int64_t lds_keys;                                   // select: candidate keys held in LDS
   size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_qovf,
       off_scratch, off_mtab, off_ovf, off_skeys, total;
@@ -145,13 +146,20 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.s_qb = (nQ + p.s_nqb - 1) / p.s_nqb;
   if (p.s_qb < 1) p.s_qb = 1;
   p.s_nqb = (nQ + p.s_qb - 1) / p.s_qb;
-  // LDS of the select kernel: room for 1.5x the expected candidate count
-  // (k * nC / S) so that several blocks share a CU; a query with more
-  // candidates selects in its global buffer instead
+  // LDS of the select kernel: room for 1.15x the expected candidate count
+  // (k * nC / S) so that four blocks share a CU (a query with more
+  // candidates selects in place in its candidate region), and T when the
+  // kernel scores raw survivors, all within 60 KB
   {
     const double expect = p.S > 0 ? (double)k * (double)nC / (double)p.S : 0.0;
-    int64_t lk = ((int64_t)(1.5 * expect) + 512 + 255) / 256 * 256;
+    int64_t lk = ((int64_t)(1.15 * expect) + 256 + 255) / 256 * 256;
     p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
+    int64_t kpad = 1;
+    while (kpad < k) kpad <<= 1;
+    const int64_t lut_bytes = (int64_t)(N + 1) * 4;
+    p.sel_lut = !p.rows && N <= 2048 && (61440 - kpad * 8 - lut_bytes) / 8 >= 1024;  // (larger T costs occupancy)
+    const int64_t cap = (61440 - kpad * 8 - (p.sel_lut ? lut_bytes : 0)) / 8;
+    if (p.lds_keys > cap) p.lds_keys = cap;
   }
   // fallback blocks: at most 16, and at most 256 MB of whole-corpus key scratch
   int64_t F = (INT64_C(256) << 20) / (8 * nC);
@@ -193,6 +201,14 @@ __device__ __forceinline__ float key_score(uint32_t k) {
   return key_float(M == BS_HAMMING ? ~k : k);
 }
 
+// A survivor of a query-lane scan: row index, x_ab and (for N < 65536, where
+// both counts fit 16 bits) the row's weight x_c, so that the select scores it
+// without gathering x_c again.
+__device__ __forceinline__ uint64_t raw_entry(uint32_t xab, int32_t xc, int64_t row, int32_t N) {
+  const uint64_t hi = N < 65536 ? (((uint64_t)(uint32_t)xc << 16) | xab) : (uint64_t)xab;
+  return (hi << 32) | (uint32_t)row;
+}
+
 // Block-wide (256 threads) inclusive scan over thread order.
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) {
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
@@ -219,12 +235,15 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) 
 template <typename K>
 __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, uint32_t* wsum,
                               K* bcast_prefix, int64_t* bcast_need, K* pmask_out = nullptr,
-                              bool early = false) {
+                              bool early = false, int top_shift = (int)sizeof(K) * 8 - 8, K prefix0 = 0,
+                              K pmask0 = 0) {
+  // (top_shift, prefix0, pmask0): every key has the bits pmask0 equal to
+  // prefix0, so the digits above top_shift need no pass
   __shared__ int done;
-  K prefix = 0, pmask = 0;
+  K prefix = prefix0, pmask = pmask0;
   int64_t need = k;
   if (threadIdx.x == 0) done = 0;
-  for (int shift = (int)sizeof(K) * 8 - 8; shift >= 0; shift -= 8) {
+  for (int shift = top_shift; shift >= 0; shift -= 8) {
     hist[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n; i += kThreads) {
@@ -297,6 +316,7 @@ struct TopkArgs {
   int64_t F;                       // fallback blocks
   int32_t N, W32, k, kpad;
   int32_t qpl, rows, split;        // scan variant: queries per lane, row-lane scan, word-split scan
+  int32_t sel_lut;                 // the select keeps T in LDS
 };
 
 // Member-wise copy through the constant address space, so that the fields of
@@ -343,6 +363,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.qpl = c->qpl;
   a.rows = c->rows;
   a.split = c->split;
+  a.sel_lut = c->sel_lut;
   return a;
 }
 
@@ -634,6 +655,7 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     for (int w = 0; w < PS; ++w) cur[w] = r0[w];
   }
   int32_t x1 = popC[c_begin];                                       // weight of row c
+  int32_t xcur = x1;
   uint16_t m[QPL];
 #pragma unroll
   for (int j = 0; j < QPL; ++j) m[j] = mt[(size_t)x1 * a.nQp + moff[j]];
@@ -674,11 +696,12 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     for (int j = 0; j < QPL; ++j) {
       const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
       if (take) {
-        if (cnt[j] < a.scap) dst[j][cnt[j]] = ((uint64_t)acc[j] << 32) | (uint32_t)c;
+        if (cnt[j] < a.scap) dst[j][cnt[j]] = raw_entry(acc[j], xcur, c, a.N);
         ++cnt[j];
       }
       m[j] = mn[j];
     }
+    xcur = x2;
     x2 = x3;
   }
 #pragma unroll
@@ -728,7 +751,7 @@ __device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid
     if (c == next_s) next_s += a.stride;
     const bool take = q_ok && !in_sample && acc >= (uint32_t)m;
     if (take) {
-      if (cnt < a.scap) dst[cnt] = ((uint64_t)acc << 32) | (uint32_t)c;
+      if (cnt < a.scap) dst[cnt] = raw_entry(acc, xc, c, a.N);
       ++cnt;
     }
   }
@@ -799,7 +822,7 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
       const int32_t xc = popC[c];
       const uint16_t m = mt[(size_t)xc * a.nQp];
       if (q_ok && !in_sample && x >= (uint32_t)m) {
-        if (cnt < a.scap) dst[cnt] = ((uint64_t)x << 32) | (uint32_t)c;
+        if (cnt < a.scap) dst[cnt] = raw_entry(x, xc, c, a.N);
         ++cnt;
       }
     }
@@ -912,8 +935,39 @@ template <int M>
 __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a,
                                  uint64_t* sel, uint32_t* hist, uint32_t* wsum, uint64_t* bprefix,
                                  int64_t* bneed, uint32_t* nsel) {
+  // the highest digit in which the keys differ: the bits above it are common
+  // to every key, so the radix select starts there
+  __shared__ uint64_t wmin[kThreads / kWave], wmax[kThreads / kWave];
+  uint64_t lo = ~(uint64_t)0, hi = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+    const uint64_t key = keys[i];
+    lo = key < lo ? key : lo;
+    hi = key > hi ? key : hi;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (threadIdx.x % kWave == 0) {
+    wmin[threadIdx.x / kWave] = lo;
+    wmax[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  lo = wmin[0];
+  hi = wmax[0];
+#pragma unroll
+  for (int w = 1; w < kThreads / kWave; ++w) {
+    lo = wmin[w] < lo ? wmin[w] : lo;
+    hi = wmax[w] > hi ? wmax[w] : hi;
+  }
+  const uint64_t diff = lo ^ hi;
+  const int top = diff ? (63 - __clzll((long long)diff)) / 8 * 8 : 0;
+  const uint64_t pmask0 = top + 8 >= 64 ? 0 : ~((((uint64_t)1) << (top + 8)) - 1);
   uint64_t pmask = 0;
-  const uint64_t kth = radix_select_kth<uint64_t>(keys, n, a.k, hist, wsum, bprefix, bneed, &pmask, true);
+  const uint64_t kth =
+      radix_select_kth<uint64_t>(keys, n, a.k, hist, wsum, bprefix, bneed, &pmask, true, top, hi & pmask0, pmask0);
   if (threadIdx.x == 0) *nsel = 0;
   for (int t = threadIdx.x; t < a.kpad; t += kThreads) sel[t] = 0;
   __syncthreads();
@@ -935,18 +989,24 @@ __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, con
 }
 
 template <int M>
-__device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, const TopkArgs& a) {
+__device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, const float* lut, const TopkArgs& a) {
   const uint32_t idx = (uint32_t)e;
-  const int32_t xab = (int32_t)(e >> 32);
-  const int32_t xc = a.popC[idx];
-  return make_key<M>(score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]), idx);
+  int32_t xab, xc;
+  if (a.N < 65536) {  // x_c travels in the entry: no gather from popC
+    xab = (int32_t)((e >> 32) & 0xFFFFu);
+    xc = (int32_t)(e >> 48);
+  } else {
+    xab = (int32_t)(e >> 32);
+    xc = a.popC[idx];
+  }
+  return make_key<M>(score_f32<M>(Tq, lut[xc], lut[xq + xc - xab]), idx);
 }
 
 // Slot entries of the query-lane scan are (x_ab << 32 | row) and are scored
 // here (RAW); the row-lane scan and the sample pass store final keys.
-template <int M, bool RAW>
+template <int M, bool RAW, bool LUT>
 __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
-  extern __shared__ uint64_t sm[];  // sel[kpad], then keys[lds_keys]
+  extern __shared__ uint64_t sm[];  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint32_t off[kSelChunk + 1];
@@ -959,6 +1019,10 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     if (threadIdx.x == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
     return;
   }
+  float* lut_s = reinterpret_cast<float*>(sm + a.kpad + a.lds_keys);
+  if (LUT)  // read after the barriers of the count below
+    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+  const float* lut = LUT ? lut_s : a.t32;
   const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
   // 1. candidate count
   uint32_t part = 0;
@@ -1001,23 +1065,35 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     if (threadIdx.x == kThreads - 1) off[kSelChunk] = incl;
     __syncthreads();
     const uint32_t T = off[kSelChunk];
-    // every thread takes output positions j = t, t + 256, ... and finds the
-    // slab of j by binary search, so no thread walks a long slab alone
-    for (uint32_t j0 = 0; j0 < T; j0 += kThreads) {
-      const uint32_t j = j0 + threadIdx.x;
-      uint64_t v = 0;
-      if (j < T) {
-        int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (off[mid] <= j) lo = mid;
-          else hi = mid - 1;
+    // every thread takes output positions j = t, t + 256, ... (four at a
+    // time, so their loads overlap) and finds the slab of j by binary search,
+    // so no thread walks a long slab alone
+    constexpr int R = 4;
+    for (uint32_t j0 = 0; j0 < T; j0 += kThreads * R) {
+      uint64_t v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t j = j0 + r * kThreads + threadIdx.x;
+        v[r] = 0;
+        if (j < T) {
+          int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= j) lo = mid;
+            else hi = mid - 1;
+          }
+          v[r] = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
         }
-        const uint64_t e = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
-        v = RAW ? cand_key<M>(e, xq, Tq, a) : e;
       }
-      if (!in_lds) __syncthreads();  // block-uniform
-      if (j < T) keys[base + j] = v;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (RAW && j0 + r * kThreads + threadIdx.x < T) v[r] = cand_key<M>(v[r], xq, Tq, lut, a);
+      if (!in_lds) __syncthreads();  // block-uniform: every source of the step read before any write
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t j = j0 + r * kThreads + threadIdx.x;
+        if (j < T) keys[base + j] = v[r];
+      }
     }
     base += T;
     __syncthreads();
@@ -1137,9 +1213,9 @@ template <bool ONE, int M, int W32T>
 __global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_rows_body<M, W32T>(a, lb)))
 }
-template <bool ONE, int M, bool RAW>
+template <bool ONE, int M, bool RAW, bool LUT>
 __global__ __launch_bounds__(kThreads) void topk_select_kernel(GroupArgs g) {
-  BS_GROUP_LOOP((select_body<M, RAW>(a, lb)))
+  BS_GROUP_LOOP((select_body<M, RAW, LUT>(a, lb)))
 }
 template <bool ONE, int M>
 __global__ __launch_bounds__(kThreads) void topk_fallback_kernel(GroupArgs g) {
@@ -1150,6 +1226,9 @@ __global__ __launch_bounds__(kThreads) void topk_fallback_kernel(GroupArgs g) {
 enum Stage { kStSample = 0, kStSampleSelect, kStBound, kStScan, kStSelect, kStFallback, kStages };
 const char* const kStageTimer[kStages] = {"topk_sample", "topk_sample", "topk_bound",
                                           "topk_scan",   "topk_select", "topk_fallback"};
+
+// The select kernel keeps T in LDS when it scores raw survivors and T is small.
+bool select_lut(const TopkArgs& a) { return a.sel_lut != 0; }
 
 // Virtual blocks of one item in one stage (0: the stage does not run).
 int64_t stage_blocks(const TopkArgs& a, int st) {
@@ -1176,7 +1255,7 @@ size_t stage_lds(const TopkArgs& a, int st) {
     case kStSampleSelect: return (size_t)a.S * 4;
     case kStBound: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
     case kStScan: return a.rows ? (size_t)(a.N + 1) * 4 : 0;
-    case kStSelect: return (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8;
+    case kStSelect: return (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8 + (select_lut(a) ? (size_t)(a.N + 1) * 4 : 0);
     default: return (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
   }
 }
@@ -1243,7 +1322,10 @@ const void* stage_kernel(const TopkArgs& a, int st) {
           default: return (const void*)topk_scan_generic_kernel<ONE, 64>;
         }
       }
-    case kStSelect: return a.rows ? (const void*)topk_select_kernel<ONE, M, false> : (const void*)topk_select_kernel<ONE, M, true>;
+    case kStSelect:
+      if (a.rows) return (const void*)topk_select_kernel<ONE, M, false, false>;
+      return select_lut(a) ? (const void*)topk_select_kernel<ONE, M, true, true>
+                           : (const void*)topk_select_kernel<ONE, M, true, false>;
     default: return (const void*)topk_fallback_kernel<ONE, M>;
   }
 }
@@ -1321,6 +1403,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.qpl = (int32_t)p.qpl;
   a.rows = p.rows ? 1 : 0;
   a.split = p.split ? 1 : 0;
+  a.sel_lut = p.sel_lut ? 1 : 0;
 }
 
 }  // namespace
@@ -1386,13 +1469,15 @@ bs_status topk_group_create(const TopkItem* items, const TopkTune* tunes, int32_
     const Plan p = make_plan(items[i].nQ, items[i].nC, items[i].N, items[i].k, tunes ? tunes[i] : dflt);
     fill_args(G->args[i], p, items[i], static_cast<char*>(item_ws[i]));
   }
-  // classes: items that share every kernel variant (width, scan mode, queries per lane)
+  // classes: items that share every kernel variant (width, scan mode, queries per lane, select LUT)
   for (int32_t i = 0; i < n; ++i) {
     if (G->args[i].nQ == 0) continue;
     int32_t c = -1;
     for (size_t j = 0; j < G->classes.size(); ++j) {
       const TopkArgs& r = G->args[G->classes[j][0]];
-      if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.qpl == G->args[i].qpl) c = (int32_t)j;
+      if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.qpl == G->args[i].qpl &&
+          r.sel_lut == G->args[i].sel_lut)
+        c = (int32_t)j;
     }
     if (c < 0) {
       G->classes.emplace_back();
