@@ -41,11 +41,11 @@ __global__ void batch_clear_kernel(int32_t* p, int32_t n) {
 std::vector<TopkTune> candidate_tunes(int32_t N) {
   std::vector<TopkTune> c;
   const int W32 = N / 32;
-  const bool small = (W32 & (W32 - 1)) == 0 && W32 <= 16;
+  const bool pow2 = (W32 & (W32 - 1)) == 0;
   const int qpls[3] = {1, 2, 4};
   const int waves[3] = {4096, 8192, 16384};
   for (int q : qpls) {
-    if (q > 1 && !small) continue;
+    if ((q == 2 && !(pow2 && W32 <= 32)) || (q == 4 && !(pow2 && W32 <= 16))) continue;
     for (int w : waves) {
       TopkTune t;
       t.qpl = q;

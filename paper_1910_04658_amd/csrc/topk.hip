@@ -86,8 +86,8 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // scan geometry: waves of QPL x 64 queries, four per block, ~16k waves
   const int W32 = N / 32;
   const bool pow2 = (W32 & (W32 - 1)) == 0;
-  p.qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && W32 == 16) ? 2 : 1);
-  if (tune.qpl == 1 || (tune.qpl == 2 && pow2 && W32 <= 16) || (tune.qpl == 4 && pow2 && W32 <= 16))
+  p.qpl = (pow2 && W32 <= 8) ? 4 : ((pow2 && (W32 == 16 || W32 == 32)) ? 2 : 1);
+  if (tune.qpl == 1 || (tune.qpl == 2 && pow2 && W32 <= 32) || (tune.qpl == 4 && pow2 && W32 <= 16))
     p.qpl = tune.qpl;
   const int64_t nqb = (nQ + 63) / 64;
   p.ngrp = (nqb + p.qpl - 1) / p.qpl;
@@ -1306,7 +1306,7 @@ const void* stage_kernel(const TopkArgs& a, int st) {
           case 4: return q == 4 ? (const void*)topk_scan_kernel<ONE, 4, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 4, 2> : (const void*)topk_scan_kernel<ONE, 4, 1>;
           case 8: return q == 4 ? (const void*)topk_scan_kernel<ONE, 8, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 8, 2> : (const void*)topk_scan_kernel<ONE, 8, 1>;
           case 16: return q == 4 ? (const void*)topk_scan_kernel<ONE, 16, 4> : q == 2 ? (const void*)topk_scan_kernel<ONE, 16, 2> : (const void*)topk_scan_kernel<ONE, 16, 1>;
-          case 32: return (const void*)topk_scan_kernel<ONE, 32, 1>;
+          case 32: return q == 2 ? (const void*)topk_scan_kernel<ONE, 32, 2> : (const void*)topk_scan_kernel<ONE, 32, 1>;
           case 64: return (const void*)topk_scan_kernel<ONE, 64, 1>;
           default: return (const void*)topk_scan_kernel<ONE, 128, 1>;
         }

@@ -15,7 +15,7 @@ namespace bs {
 
 // Tile-shape choices of the scan (0 or negative = the built-in heuristic).
 struct TopkTune {
-  int32_t qpl = 0;    // 64-query groups per wave of the query-lane scan (1, 2 or 4; 2 and 4 for N <= 512)
+  int32_t qpl = 0;    // 64-query groups per wave of the query-lane scan (1, 2 or 4; 2 for N <= 1024, 4 for N <= 512)
   int32_t waves = 0;  // approximate waves of the scan grid (sets the corpus slab length)
   int32_t rows = -1;  // 0: never use the row-lane scan; otherwise it is used for batches of <= 64 queries
 };
