@@ -43,10 +43,13 @@ std::vector<TopkTune> candidate_tunes(int32_t N) {
   const int W32 = N / 32;
   const bool pow2 = (W32 & (W32 - 1)) == 0;
   const int qpls[3] = {1, 2, 4};
-  const int waves[3] = {4096, 8192, 16384};
+  // the word-split scan (256 and 512 words) also tries a finer grid
+  const int waves[4] = {4096, 8192, 16384, 32768};
+  const int n_waves = W32 >= 256 ? 4 : 3;
   for (int q : qpls) {
     if ((q == 2 && !(pow2 && W32 <= 32)) || (q == 4 && !(pow2 && W32 <= 16))) continue;
-    for (int w : waves) {
+    for (int i = 0; i < n_waves; ++i) {
+      const int w = waves[i];
       TopkTune t;
       t.qpl = q;
       t.waves = w;

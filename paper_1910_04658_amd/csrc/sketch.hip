@@ -343,7 +343,6 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   const int bits = A.bits;
   uint32_t* table = lds;
   uint32_t* stage_base = lds + A.table_words;
-  const uint32_t emask = (1u << bits) - 1u;
 
   uint32_t errbits = 0;
   // The packed map (built by pack_map_kernel) goes to LDS 16 bytes per load,
@@ -377,7 +376,7 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   __syncthreads();
 
   // 2. each wave owns a contiguous range of rows, in windows of G rows
-  const int wid = threadIdx.x / kWave;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int W32 = a.W32;
   uint32_t* sk = stage_base + (size_t)wid * a.stride;
@@ -437,28 +436,37 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   // differs from the prefetched one reloads.
   const int64_t nnz = a.nnz;
   const int64_t wave_end = rw0 < rw1 ? (int64_t)a.indptr[rw1] : 0;  // prefetch bound only
+  // Element positions fit 32 bits (nnz <= INT32_MAX), so every position and
+  // row-start comparison below is a scalar 32-bit operation.
   uint32_t nidx[kUnrollLds];
-  int64_t pf_base = -1;
-  auto prefetch = [&](int64_t b) {
+  uint32_t pf_base = UINT32_MAX;  // start of the chunk whose indices are in flight
+  auto prefetch = [&](uint32_t b) {
     pf_base = b;
-    if (b >= 0 && b + (int64_t)kWave * kUnrollLds <= nnz) {
+    if ((int64_t)b + (int64_t)kWave * kUnrollLds <= nnz) {
       const int32_t* src = a.indices + b + lane;
 #pragma unroll
       for (int u = 0; u < kUnrollLds; ++u) nidx[u] = (uint32_t)__builtin_nontemporal_load(src + u * kWave);
-    } else {  // positions fit 32 bits: nnz <= 2^31 - 1
-      const uint32_t ub = b < 0 ? 0u : (uint32_t)b, last = (uint32_t)(nnz - 1);
+    } else {
+      const uint32_t last = (uint32_t)(nnz - 1);
 #pragma unroll
       for (int u = 0; u < kUnrollLds; ++u) {
-        const uint32_t pos = ub + (uint32_t)(u * kWave + lane);
+        const uint32_t pos = b + (uint32_t)(u * kWave + lane);
         nidx[u] = (uint32_t)__builtin_nontemporal_load(a.indices + (pos < last ? pos : last));
       }
     }
   };
-  if (rw0 < rw1 && nnz > 0) prefetch((int64_t)__builtin_amdgcn_readfirstlane(p_next));
+  if (rw0 < rw1 && nnz > 0) {
+    const int32_t b = __builtin_amdgcn_readfirstlane(p_next);
+    prefetch(b < 0 ? 0u : (uint32_t)b);
+  }
   const uint32_t row_bytes = (uint32_t)W32 * 4u;
   const uint32_t sk_b = lds_addr(sk), table_b = lds_addr(table);
   const uint32_t dmax = d32 - 1u;
-  uint64_t badmask = 0;  // lanes that met an index outside [0, d)
+  const uint32_t wbits = (uint32_t)bits - 5u;  // bits of a target's word index (N >= 64)
+  // Largest index loaded. Every loaded element lies in [0, nnz) (tail loads
+  // are clamped there), so an index outside [0, d) anywhere in the input is
+  // reported, as with a per-element check.
+  uint32_t imax = 0;
   for (int64_t r0 = rw0; r0 < rw1; r0 += a.G) {
     const int g = (int)(rw1 - r0 < a.G ? rw1 - r0 : a.G);
     const int32_t p = p_next;
@@ -478,11 +486,12 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (window_bad) errbits |= BS_FLAG_INDPTR;
     if (!window_bad) {
-      const int64_t e0 = __builtin_amdgcn_readfirstlane(p);
-      const int64_t e1 = __builtin_amdgcn_readlane(p, g);
-      int cur = 0;
-      int64_t nxt = (g > 1) ? (int64_t)__builtin_amdgcn_readlane(p, 1) : INT64_MAX;
-      for (int64_t base = e0; base < e1; base += (int64_t)kWave * kUnrollLds) {
+      const uint32_t e0 = (uint32_t)__builtin_amdgcn_readfirstlane(p);
+      const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane(p, g);
+      // lanes 1 .. g-1 of p hold the window's row starts after the first
+      const uint64_t starts = __ballot(lane >= 1 && lane < g);
+      uint32_t c_prev = 0;  // row starts before the current slice
+      for (uint32_t base = e0; base < e1; base += kWave * kUnrollLds) {
         // Element u of lane l sits at base + u*64 + l. A full chunk has no
         // per-element branches; the last chunk of a window skips its empty
         // 64-element slices with a uniform branch and masks the lanes past
@@ -494,26 +503,30 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
 #pragma unroll
         for (int u = 0; u < kUnrollLds; ++u) idx[u] = nidx[u];
         {
-          const int64_t next = base + (int64_t)kWave * kUnrollLds < e1 ? base + (int64_t)kWave * kUnrollLds : e1;
-          if (next < wave_end) prefetch(next);
-          else pf_base = -1;
+          const uint32_t next = e1 - base > (uint32_t)(kWave * kUnrollLds) ? base + kWave * kUnrollLds : e1;
+          if ((int64_t)next < wave_end) prefetch(next);
+          else pf_base = UINT32_MAX;
         }
         auto chunk = [&](auto full_tag) {
           constexpr bool FULL = decltype(full_tag)::value;
-          const int rem = FULL ? kWave * kUnrollLds : (int)(e1 - base);
-          // LDS byte address of the stage row of slice u's elements: every
-          // 64-element slice starts at a uniform row; a row start inside the
-          // slice moves the lanes past it one row on (rows are longer than a
-          // slice on average, so this is about one compare per row start).
-          // Slices are taken in order, just before their ORs.
+          const uint32_t rem = FULL ? (uint32_t)(kWave * kUnrollLds) : e1 - base;
+          // Stage-row LDS byte address of each lane's element in slice u: the
+          // row starts up to the slice's last element are counted with one
+          // ballot; each start inside the slice moves the lanes at and past
+          // it one row on (rows are longer than a slice on average, so this
+          // is rarely more than one step). Slices are taken in order.
           auto slice_rows = [&](int u) {
-            uint32_t ro = sk_b + (uint32_t)cur * row_bytes;
-            const int64_t s0 = base + u * kWave;
-            while (nxt < s0 + kWave) {  // wave-uniform
-              ro += (lane >= (int)(nxt - s0)) ? row_bytes : 0u;
-              ++cur;
-              nxt = (cur + 1 < g) ? (int64_t)__builtin_amdgcn_readlane(p, cur + 1) : INT64_MAX;
+            const uint32_t s0 = base + (uint32_t)(u * kWave);
+            const uint32_t c_hi = (uint32_t)__popcll(__ballot((uint32_t)p <= s0 + (kWave - 1)) & starts);
+            uint32_t ro = sk_b + c_prev * row_bytes;
+            if (c_hi != c_prev) {  // wave-uniform; starts c_prev+1 .. c_hi lie in the slice
+              uint32_t i = c_prev;
+              do {
+                ++i;
+                ro += (uint32_t)lane >= (uint32_t)__builtin_amdgcn_readlane(p, i) - s0 ? row_bytes : 0u;
+              } while (i != c_hi);
             }
+            c_prev = c_hi;
             return ro;
           };
           // table word pairs, half a chunk at a time: addresses, then 16 reads
@@ -522,17 +535,17 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
           constexpr int H = kUnrollLds / 2;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
-            if (!FULL && h * H * kWave >= rem) break;  // wave-uniform: the rest is past the end
+            if (!FULL && (uint32_t)(h * H * kWave) >= rem) break;  // wave-uniform: the rest is past the end
             uint32_t bp[H], lo[H], hi[H];
 #pragma unroll
             for (int v = 0; v < H; ++v) {
               const int u = h * H + v;
-              badmask |= __ballot((FULL || u * kWave + lane < rem) && idx[u] > dmax);
+              imax = idx[u] > imax ? idx[u] : imax;
               bp[v] = __umul24(idx[u] < dmax ? idx[u] : dmax, (uint32_t)bits);
             }
 #pragma unroll
             for (int v = 0; v < H; ++v) {
-              const lds_u32* tw = lds_ptr(table_b + (__builtin_amdgcn_ubfe(bp[v], 5, 27) << 2));
+              const lds_u32* tw = lds_ptr(table_b + ((bp[v] >> 5) << 2));
               lo[v] = tw[0];
               hi[v] = tw[1];
             }
@@ -540,15 +553,18 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
 #pragma unroll
             for (int v = 0; v < H; ++v) {
               const int u = h * H + v;
-              if (!FULL && u * kWave >= rem) break;  // wave-uniform
+              if (!FULL && (uint32_t)(u * kWave) >= rem) break;  // wave-uniform
               const uint32_t ro = slice_rows(u);
-              const uint32_t jj = __builtin_amdgcn_alignbit(hi[v], lo[v], bp[v]) & emask;
-              const uint32_t addr = ro + (__builtin_amdgcn_ubfe(jj, 5, 27) << 2);
-              if (FULL || u * kWave + lane < rem) __atomic_fetch_or(lds_ptr(addr), 1u << (jj & 31), __ATOMIC_RELAXED);
+              // target in the low `bits` bits of t (higher bits are the next
+              // entries): word t[bits-1:5] of the row, bit t[4:0]
+              const uint32_t t = __builtin_amdgcn_alignbit(hi[v], lo[v], bp[v]);
+              const uint32_t addr = ro + (__builtin_amdgcn_ubfe(t, 5, wbits) << 2);
+              if (FULL || (uint32_t)(u * kWave + lane) < rem)
+                __atomic_fetch_or(lds_ptr(addr), 1u << (t & 31), __ATOMIC_RELAXED);
             }
           }
         };
-        if (base + (int64_t)kWave * kUnrollLds <= e1) chunk(std::true_type());
+        if (e1 - base >= (uint32_t)(kWave * kUnrollLds)) chunk(std::true_type());
         else chunk(std::false_type());
       }
     }
@@ -568,7 +584,7 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (a.pop && lane < g) a.pop[r0 + lane] = (int32_t)cnt[lane];
   }
-  if (badmask) errbits |= BS_FLAG_INDEX;
+  if (imax > dmax) errbits |= BS_FLAG_INDEX;
   errbits |= range_err;
   if (a.err && errbits) atomicOr(a.err, (int32_t)errbits);
 }

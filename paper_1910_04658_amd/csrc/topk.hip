@@ -31,6 +31,7 @@
 #include <string.h>
 
 #include <memory>
+#include <type_traits>
 #include <vector>
 
 #include "bs_common.h"
@@ -52,6 +53,7 @@ constexpr int kScanWaves = 16384;    // waves of the scan grid, about
 constexpr int kRowWaves = 4096;      // waves of the row-lane scan (small batches)
 constexpr int kRowsMaxQ = 64;        // largest batch of the row-lane scan
 constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the word-split scan
+constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, about
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFallbackBlocks = 16;
 
@@ -104,7 +106,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   if (p.split) {
     p.ngrp = nqb;
     p.nqb4 = nqb;  // one block per (row slab, query group)
-    const int64_t waves = tune.waves > 0 ? tune.waves : kScanWaves;
+    const int64_t waves = tune.waves > 0 ? tune.waves : kSplitGridWaves;
     int64_t rslabs = p.ngrp > 0 ? (waves + kSplitWaves * p.ngrp - 1) / (kSplitWaves * p.ngrp) : 1;
     if (rslabs > nC) rslabs = nC;
     if (rslabs < 1) rslabs = 1;
@@ -633,10 +635,10 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
   }
   // threshold-table columns; groups past the last one read group qg0 (masked by q_ok)
   const int64_t ngroups = a.nQp / kWave;
-  int64_t moff[QPL];
-#pragma unroll
-  for (int j = 0; j < QPL; ++j) moff[j] = (qg0 + j < ngroups ? qg0 + j : qg0) * kWave + lane;
   const uint16_t* mt = a.mtab;
+  uint32_t moff[QPL];  // byte offsets of this lane's columns in a table row
+#pragma unroll
+  for (int j = 0; j < QPL; ++j) moff[j] = (uint32_t)((qg0 + j < ngroups ? qg0 + j : qg0) * kWave + lane) * 2u;
   int cnt[QPL];
   uint64_t* dst[QPL];  // this (query, slab)'s slot range
 #pragma unroll
@@ -644,26 +646,43 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     cnt[j] = 0;
     dst[j] = a.cands + (size_t)(q_ok[j] ? q[j] : 0) * a.kmax + a.S + sl * a.scap;
   }
-  int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row
-  const int64_t s_end = a.S * a.stride;
-
-  // scalar pipeline state: current piece words, row weights two rows ahead
-  uint32_t cur[PS];
+  // row indices fit 32 bits (nC <= INT32_MAX); next_s is the next sampled
+  // row of the slab, -1 once the sample ends
+  const int32_t cb = (int32_t)c_begin, ce = (int32_t)c_end, stride = (int32_t)a.stride;
+  const int64_t s_end64 = a.S * a.stride < a.nC ? a.S * a.stride : a.nC;
+  const uint32_t s_end = (uint32_t)s_end64;
+  int32_t next_s;
   {
-    const cptr<uint32_t> r0 = as_const(C32 + (size_t)c_begin * W32T);
-#pragma unroll
-    for (int w = 0; w < PS; ++w) cur[w] = r0[w];
+    const int64_t n = (c_begin + a.stride - 1) / a.stride * a.stride;
+    next_s = n < s_end64 ? (int32_t)n : -1;
   }
-  int32_t x1 = popC[c_begin];                                       // weight of row c
-  int32_t xcur = x1;
-  uint16_t m[QPL];
-#pragma unroll
-  for (int j = 0; j < QPL; ++j) m[j] = mt[(size_t)x1 * a.nQp + moff[j]];
-  int32_t x2 = popC[c_begin + 1 < c_end ? c_begin + 1 : c_begin];  // weight of row c+1
 
-  for (int64_t c = c_begin; c < c_end; ++c) {
-    const int64_t c1 = c + 1 < c_end ? c + 1 : c;
-    const int64_t c2 = c + 2 < c_end ? c + 2 : c1;
+  // Scalar pipeline: the pieces of consecutive rows land alternately in two
+  // register sets (the one in use and the one being fetched), so no fetched
+  // word is ever moved; row weights run two rows ahead, threshold columns one.
+  uint32_t buf[2][PS];
+  {
+    const cptr<uint32_t> r0 = as_const(C32 + (size_t)(uint32_t)cb * W32T);
+#pragma unroll
+    for (int w = 0; w < PS; ++w) buf[0][w] = r0[w];
+  }
+  auto mrow = [&](int32_t x) {  // row x of the threshold table (uniform)
+    return reinterpret_cast<const char*>(mt + (size_t)(uint32_t)x * (uint32_t)a.nQp);
+  };
+  int32_t xcur = popC[cb];  // weight of the current row
+  uint16_t m[QPL];
+  {
+    const char* mr = mrow(xcur);
+#pragma unroll
+    for (int j = 0; j < QPL; ++j) m[j] = *reinterpret_cast<const uint16_t*>(mr + moff[j]);
+  }
+  int32_t x2 = popC[cb + 1 < ce ? cb + 1 : cb];  // weight of the next row
+
+  // one row; PH: register set holding the row's first piece
+  auto row = [&](const int32_t c, auto ph) {
+    constexpr int PH = decltype(ph)::value;
+    const int32_t c1 = c + 1 < ce ? c + 1 : c;
+    const int32_t c2 = c1 + 1 < ce ? c1 + 1 : c1;
     uint32_t acc[QPL];
 #pragma unroll
     for (int j = 0; j < QPL; ++j) acc[j] = 0;
@@ -671,27 +690,31 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     uint16_t mn[QPL];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+      uint32_t(&use)[PS] = buf[(PH + p) & 1];
+      uint32_t(&fill)[PS] = buf[(PH + p + 1) & 1];
       // fetch the next piece (the next row's first piece after the last one)
-      uint32_t nxt[PS];
-      const cptr<uint32_t> nr = as_const(C32 + (p + 1 < P ? (size_t)c * W32T + (p + 1) * PS : (size_t)c1 * W32T));
+      const cptr<uint32_t> nr =
+          as_const(C32 + (p + 1 < P ? (size_t)(uint32_t)c * W32T + (p + 1) * PS : (size_t)(uint32_t)c1 * W32T));
 #pragma unroll
-      for (int w = 0; w < PS; ++w) nxt[w] = nr[w];
+      for (int w = 0; w < PS; ++w) fill[w] = nr[w];
       if (p == 0) {
         x3 = popC[c2];
+        const char* mr = mrow(x2);
 #pragma unroll
-        for (int j = 0; j < QPL; ++j) mn[j] = mt[(size_t)x2 * a.nQp + moff[j]];
+        for (int j = 0; j < QPL; ++j) mn[j] = *reinterpret_cast<const uint16_t*>(mr + moff[j]);
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int j = 0; j < QPL; ++j) {
 #pragma unroll
-        for (int w = 0; w < PS; ++w) acc[j] = bcnt_add(cur[w] & qw[j][p * PS + w], acc[j]);
+        for (int w = 0; w < PS; ++w) acc[j] = bcnt_add(use[w] & qw[j][p * PS + w], acc[j]);
       }
-#pragma unroll
-      for (int w = 0; w < PS; ++w) cur[w] = nxt[w];
     }
-    const bool in_sample = c == next_s && c < s_end;
-    if (c == next_s) next_s += a.stride;
+    const bool in_sample = c == next_s;
+    if (in_sample) {
+      const uint32_t n = (uint32_t)next_s + (uint32_t)stride;
+      next_s = n < s_end ? (int32_t)n : -1;
+    }
 #pragma unroll
     for (int j = 0; j < QPL; ++j) {
       const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
@@ -703,6 +726,14 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     }
     xcur = x2;
     x2 = x3;
+  };
+  if constexpr (P % 2 == 0) {  // every row starts in set 0
+    for (int32_t c = cb; c < ce; ++c) row(c, std::integral_constant<int, 0>());
+  } else {  // rows alternate between the sets: two rows per iteration
+    for (uint32_t c = (uint32_t)cb; c < (uint32_t)ce; c += 2) {
+      row((int32_t)c, std::integral_constant<int, 0>());
+      if (c + 1 < (uint32_t)ce) row((int32_t)c + 1, std::integral_constant<int, 1>());
+    }
   }
 #pragma unroll
   for (int j = 0; j < QPL; ++j) {
