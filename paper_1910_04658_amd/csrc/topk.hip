@@ -48,7 +48,7 @@ constexpr int kThreads = 256;
 constexpr int kSampleMin = 4096;     // rows scored in the sample pass
 constexpr int kSampleMax = 15360;  // keys fit 60 KB of LDS in the sample select
 constexpr int kSelectLdsKeys = 6144; // candidate keys selected in LDS (else in a global buffer)
-constexpr int kSelChunk = 1024;      // slabs compacted per step of the select kernel
+constexpr int kMaxSlabs = 2048;      // slot slabs per query at most (the select reads every count at once)
 constexpr int kScanWaves = 16384;    // waves of the scan grid, about
 constexpr int kRowWaves = 4096;      // waves of the row-lane scan (small batches)
 constexpr int kRowsMaxQ = 64;        // largest batch of the row-lane scan
@@ -108,17 +108,21 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
     p.nqb4 = nqb;  // one block per (row slab, query group)
     const int64_t waves = tune.waves > 0 ? tune.waves : kSplitGridWaves;
     int64_t rslabs = p.ngrp > 0 ? (waves + kSplitWaves * p.ngrp - 1) / (kSplitWaves * p.ngrp) : 1;
+    if (rslabs > kMaxSlabs / kSplitWaves) rslabs = kMaxSlabs / kSplitWaves;
     if (rslabs > nC) rslabs = nC;
     if (rslabs < 1) rslabs = 1;
     p.slab = (nC + rslabs - 1) / rslabs;
   } else if (p.rows) {
     const int64_t waves = tune.waves > 0 ? tune.waves : kRowWaves;
     const int64_t tiles = (nC + kWave - 1) / kWave;
-    const int64_t tpw = (tiles + waves - 1) / waves;
+    int64_t tpw = (tiles + waves - 1) / waves;
+    const int64_t tpw_min = (tiles + kMaxSlabs - 1) / kMaxSlabs;
+    if (tpw < tpw_min) tpw = tpw_min;
     p.slab = tpw * kWave;
   } else {
     const int64_t waves = tune.waves > 0 ? tune.waves : kScanWaves;
     int64_t n_slabs = p.ngrp > 0 ? (waves + p.ngrp - 1) / p.ngrp : 1;
+    if (n_slabs > kMaxSlabs) n_slabs = kMaxSlabs;
     if (n_slabs > nC) n_slabs = nC;
     if (n_slabs < 1) n_slabs = 1;
     p.slab = (nC + n_slabs - 1) / n_slabs;
@@ -148,13 +152,13 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.s_qb = (nQ + p.s_nqb - 1) / p.s_nqb;
   if (p.s_qb < 1) p.s_qb = 1;
   p.s_nqb = (nQ + p.s_qb - 1) / p.s_qb;
-  // LDS of the select kernel: room for 1.15x the expected candidate count
-  // (k * nC / S) so that four blocks share a CU (a query with more
-  // candidates selects in place in its candidate region), and T when the
-  // kernel scores raw survivors, all within 60 KB
+  // LDS of the select kernel: room for 1.25x the expected candidate count
+  // (k * nC / S) plus 512, about four standard deviations of the count for
+  // k = 100 (a query with more candidates selects in place in its candidate
+  // region), and T when the kernel scores raw survivors, all within 60 KB
   {
     const double expect = p.S > 0 ? (double)k * (double)nC / (double)p.S : 0.0;
-    int64_t lk = ((int64_t)(1.15 * expect) + 256 + 255) / 256 * 256;
+    int64_t lk = ((int64_t)(1.25 * expect) + 512 + 255) / 256 * 256;
     p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
     int64_t kpad = 1;
     while (kpad < k) kpad <<= 1;
@@ -227,6 +231,21 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) 
   return v + add;
 }
 
+// Largest v over the block (block-wide call).
+__device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* wsum) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const uint32_t o = __shfl_xor(v, off);
+    v = o > v ? o : v;
+  }
+  if (threadIdx.x % kWave == 0) wsum[threadIdx.x / kWave] = v;
+  __syncthreads();
+  uint32_t m = 0;
+  for (int w = 0; w < kThreads / kWave; ++w) m = wsum[w] > m ? wsum[w] : m;
+  __syncthreads();
+  return m;
+}
+
 // MSB-first radix select over 8-bit digits of the k largest of n keys
 // (1 <= k <= n). On return the k largest are exactly the keys with
 // (key & *pmask_out) >= prefix (the return value): either all digits were
@@ -238,14 +257,16 @@ template <typename K>
 __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, uint32_t* wsum,
                               K* bcast_prefix, int64_t* bcast_need, K* pmask_out = nullptr,
                               bool early = false, int top_shift = (int)sizeof(K) * 8 - 8, K prefix0 = 0,
-                              K pmask0 = 0) {
+                              K pmask0 = 0, int min_shift = 0) {
   // (top_shift, prefix0, pmask0): every key has the bits pmask0 equal to
-  // prefix0, so the digits above top_shift need no pass
+  // prefix0, so the digits above top_shift need no pass. Digits below
+  // min_shift are not resolved: the result is then the lower edge of the
+  // bin holding the k-th key (a lower bound on it).
   __shared__ int done;
   K prefix = prefix0, pmask = pmask0;
   int64_t need = k;
   if (threadIdx.x == 0) done = 0;
-  for (int shift = top_shift; shift >= 0; shift -= 8) {
+  for (int shift = top_shift; shift >= min_shift; shift -= 8) {
     hist[threadIdx.x] = 0;
     __syncthreads();
     for (int64_t i = threadIdx.x; i < n; i += kThreads) {
@@ -275,8 +296,66 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
   return prefix;
 }
 
+// Smallest and largest of n keys (block-wide call; the keys widened to 64
+// bits). The radix selects start at the highest digit where they differ.
+template <typename K>
+__device__ void block_key_range(const K* keys, int64_t n, uint64_t* lo_out, uint64_t* hi_out) {
+  __shared__ uint64_t wmin[kThreads / kWave], wmax[kThreads / kWave];
+  uint64_t lo = ~(uint64_t)0, hi = 0;
+  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+    const uint64_t key = keys[i];
+    lo = key < lo ? key : lo;
+    hi = key > hi ? key : hi;
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
+    lo = l2 < lo ? l2 : lo;
+    hi = h2 > hi ? h2 : hi;
+  }
+  if (threadIdx.x % kWave == 0) {
+    wmin[threadIdx.x / kWave] = lo;
+    wmax[threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  lo = wmin[0];
+  hi = wmax[0];
+#pragma unroll
+  for (int w = 1; w < kThreads / kWave; ++w) {
+    lo = wmin[w] < lo ? wmin[w] : lo;
+    hi = wmax[w] > hi ? wmax[w] : hi;
+  }
+  *lo_out = lo;
+  *hi_out = hi;
+}
+
+
 // Descending bitonic sort of n (power of two, <= 2 * kThreads * 8) keys in LDS.
 __device__ void bitonic_sort_desc(uint64_t* v, int n) {
+  if (n <= 2 * kWave) {  // every pair belongs to wave 0: its own LDS order suffices, no block barriers
+    if (threadIdx.x < kWave) {
+      const int t = threadIdx.x;
+      for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          if (t < n / 2) {
+            const int lo = 2 * t - (t & (stride - 1));
+            const int hi = lo + stride;
+            const bool desc = ((lo & size) == 0);
+            const uint64_t a = v[lo], b = v[hi];
+            if (desc ? (a < b) : (a > b)) {
+              v[lo] = b;
+              v[hi] = a;
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+    }
+    __syncthreads();
+    return;
+  }
   for (int size = 2; size <= n; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int t = threadIdx.x; t < n / 2; t += kThreads) {
@@ -302,9 +381,10 @@ struct TopkArgs {
   const int32_t* __restrict__ popC;
   QConst* __restrict__ qc;
   int32_t* __restrict__ cnts;      // [nQ] sample candidates per query
-  uint64_t* __restrict__ cands;    // [nQ][kmax]: S sample candidates (keys), then n_slabs x scap scan
-                                   // candidates (keys from the row-lane scan, x_ab << 32 | row from the
-                                   // query-lane scan); compacted in place into keys by the select
+  uint64_t* __restrict__ cands;    // [nQ][kmax]: S sample candidates (keys), then scap planes of n_slabs
+                                   // scan candidates (slot c of slab s at S + c*n_slabs + s; keys from
+                                   // the row-lane scan, raw (x_c, x_ab, row) entries from the query-lane
+                                   // scans); compacted into keys by the select
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
   uint64_t* __restrict__ scratch;  // [F][nC]
@@ -446,22 +526,49 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
 #pragma unroll
     for (int w = 0; w < R; ++w) cw[w] = crow[w];
   }
-  for (int64_t q = q_begin; q < q_end; ++q) {
-    const cptr<uint32_t> qrow = as_const(reinterpret_cast<const uint32_t*>(a.Q) + (size_t)q * W32);
-    uint32_t acc = 0;
-    if (W32T) {
+  const uint32_t* Q32 = reinterpret_cast<const uint32_t*>(a.Q);
+  const cptr<int32_t> popQ = as_const(a.popQ);
+  auto emit = [&](int64_t q, uint32_t acc, int32_t xq) {
+    const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc]);
+    if (i_ok) a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
+  };
+  if (W32T) {
+    // query words on the scalar unit, fetched one query ahead into two
+    // register sets used in turn (no fetched word is moved)
+    uint32_t qw[2][R];
+    int32_t xq[2];
+    auto fetch = [&](int b, int64_t q) {
+      const cptr<uint32_t> qrow = as_const(Q32 + (size_t)q * W32T);
 #pragma unroll
-      for (int w = 0; w < R; ++w) acc = bcnt_add(qrow[w] & cw[w], acc);
-    } else {
+      for (int w = 0; w < R; ++w) qw[b][w] = qrow[w];
+      xq[b] = popQ[q];
+    };
+    auto count = [&](int b) {
+      uint32_t acc = 0;
+#pragma unroll
+      for (int w = 0; w < R; ++w) acc = bcnt_add(qw[b][w] & cw[w], acc);
+      return acc;
+    };
+    if (q_begin < q_end) fetch(0, q_begin);
+    for (int64_t q = q_begin; q < q_end; q += 2) {
+      if (q + 1 < q_end) fetch(1, q + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      emit(q, count(0), xq[0]);
+      if (q + 1 < q_end) {
+        if (q + 2 < q_end) fetch(0, q + 2);
+        __builtin_amdgcn_sched_barrier(0);
+        emit(q + 1, count(1), xq[1]);
+      }
+    }
+  } else {
+    for (int64_t q = q_begin; q < q_end; ++q) {
+      const cptr<uint32_t> qrow = as_const(Q32 + (size_t)q * W32);
+      uint32_t acc = 0;
       for (int w = 0; w < W32; w += 2) {
         const uint2 c2 = *reinterpret_cast<const uint2*>(crow + w);
         acc += popc32(qrow[w] & c2.x) + popc32(qrow[w + 1] & c2.y);
       }
-    }
-    const int32_t xq = as_const(a.popQ)[q];
-    const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc]);
-    if (i_ok) {
-      a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
+      emit(q, acc, popQ[q]);
     }
   }
 }
@@ -522,8 +629,9 @@ __device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx,
   }
 }
 
-// 1b. Per query: the k-th best sample key (LDS radix select), the sample rows
-// scoring at least that, and the per-query constants of the scan filter.
+// 1b. Per query: a lower bound tau on the k-th best sample key (LDS radix
+// select), the sample rows scoring at least tau, and the per-query constants
+// of the scan filter.
 template <int M>
 __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint32_t keys[];  // [S]
@@ -540,7 +648,17 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
     a.ovf[1] = 0;
   }
   __syncthreads();
-  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed);
+  // tau: the k-th best sample key to its top 24 bits, from the highest digit
+  // where the keys differ. The lower edge of its bin is a lower bound on it,
+  // which is all the filter needs: every row scoring at least tau becomes a
+  // candidate, and the final selection is exact.
+  uint64_t klo, khi;
+  block_key_range(keys, a.S, &klo, &khi);
+  const uint32_t diff = (uint32_t)(klo ^ khi);
+  const int top = diff ? (31 - __clz((int)diff)) / 8 * 8 : 0;
+  const uint32_t pmask0 = top + 8 >= 32 ? 0u : ~((1u << (top + 8)) - 1u);
+  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed, nullptr, true,
+                                                      top, (uint32_t)khi & pmask0, pmask0, top < 8 ? top : 8);
   uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     if (keys[i] >= tau_key) {
@@ -644,7 +762,7 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
   for (int j = 0; j < QPL; ++j) {
     cnt[j] = 0;
-    dst[j] = a.cands + (size_t)(q_ok[j] ? q[j] : 0) * a.kmax + a.S + sl * a.scap;
+    dst[j] = a.cands + (size_t)(q_ok[j] ? q[j] : 0) * a.kmax + a.S + sl;
   }
   // row indices fit 32 bits (nC <= INT32_MAX); next_s is the next sampled
   // row of the slab, -1 once the sample ends
@@ -719,7 +837,7 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     for (int j = 0; j < QPL; ++j) {
       const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
       if (take) {
-        if (cnt[j] < a.scap) dst[j][cnt[j]] = raw_entry(acc[j], xcur, c, a.N);
+        if (cnt[j] < a.scap) dst[j][(size_t)cnt[j] * a.n_slabs] = raw_entry(acc[j], xcur, c, a.N);
         ++cnt[j];
       }
       m[j] = mn[j];
@@ -763,7 +881,7 @@ __device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid
   const uint32_t* C32 = reinterpret_cast<const uint32_t*>(a.C);
   const uint16_t* mt = a.mtab + q;
   int cnt = 0;
-  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + sl * a.scap;
+  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + sl;
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;
   const int64_t s_end = a.S * a.stride;
   for (int64_t c = c_begin; c < c_end; ++c) {
@@ -782,7 +900,7 @@ __device__ __forceinline__ void scan_generic_body(const TopkArgs& a, int64_t bid
     if (c == next_s) next_s += a.stride;
     const bool take = q_ok && !in_sample && acc >= (uint32_t)m;
     if (take) {
-      if (cnt < a.scap) dst[cnt] = raw_entry(acc, xc, c, a.N);
+      if (cnt < a.scap) dst[(size_t)cnt * a.n_slabs] = raw_entry(acc, xc, c, a.N);
       ++cnt;
     }
   }
@@ -824,7 +942,7 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
   }
   const int64_t ss = rs * kSplitWaves + wid;  // this wave's slot slab
   int cnt = 0;
-  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + ss * a.scap;
+  uint64_t* dst = a.cands + (size_t)(q_ok ? q : 0) * a.kmax + a.S + ss;
   const uint16_t* mt = a.mtab + q;  // q < nQp
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row at or after the rows seen
   const int64_t s_end = a.S * a.stride;
@@ -853,7 +971,7 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
       const int32_t xc = popC[c];
       const uint16_t m = mt[(size_t)xc * a.nQp];
       if (q_ok && !in_sample && x >= (uint32_t)m) {
-        if (cnt < a.scap) dst[cnt] = raw_entry(x, xc, c, a.N);
+        if (cnt < a.scap) dst[(size_t)cnt * a.n_slabs] = raw_entry(x, xc, c, a.N);
         ++cnt;
       }
     }
@@ -947,7 +1065,7 @@ __device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
           if (slot < a.scap) {
             const float sc = score_f32<M>(lut[popQ[q]], Tc, Tu);
-            a.cands[(size_t)q * a.kmax + a.S + sl * a.scap + slot] = make_key<M>(sc, (uint32_t)rr);
+            a.cands[(size_t)q * a.kmax + a.S + (size_t)slot * a.n_slabs + sl] = make_key<M>(sc, (uint32_t)rr);
           }
         }
         if (lane == q) cntv += __popcll(bal);
@@ -968,31 +1086,8 @@ __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, con
                                  int64_t* bneed, uint32_t* nsel) {
   // the highest digit in which the keys differ: the bits above it are common
   // to every key, so the radix select starts there
-  __shared__ uint64_t wmin[kThreads / kWave], wmax[kThreads / kWave];
-  uint64_t lo = ~(uint64_t)0, hi = 0;
-  for (int64_t i = threadIdx.x; i < n; i += kThreads) {
-    const uint64_t key = keys[i];
-    lo = key < lo ? key : lo;
-    hi = key > hi ? key : hi;
-  }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    const uint64_t l2 = __shfl_xor(lo, off), h2 = __shfl_xor(hi, off);
-    lo = l2 < lo ? l2 : lo;
-    hi = h2 > hi ? h2 : hi;
-  }
-  if (threadIdx.x % kWave == 0) {
-    wmin[threadIdx.x / kWave] = lo;
-    wmax[threadIdx.x / kWave] = hi;
-  }
-  __syncthreads();
-  lo = wmin[0];
-  hi = wmax[0];
-#pragma unroll
-  for (int w = 1; w < kThreads / kWave; ++w) {
-    lo = wmin[w] < lo ? wmin[w] : lo;
-    hi = wmax[w] > hi ? wmax[w] : hi;
-  }
+  uint64_t lo, hi;
+  block_key_range(keys, n, &lo, &hi);
   const uint64_t diff = lo ^ hi;
   const int top = diff ? (63 - __clzll((long long)diff)) / 8 * 8 : 0;
   const uint64_t pmask0 = top + 8 >= 64 ? 0 : ~((((uint64_t)1) << (top + 8)) - 1);
@@ -1033,102 +1128,101 @@ __device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, c
   return make_key<M>(score_f32<M>(Tq, lut[xc], lut[xq + xc - xab]), idx);
 }
 
-// Slot entries of the query-lane scan are (x_ab << 32 | row) and are scored
-// here (RAW); the row-lane scan and the sample pass store final keys.
+// Slot entries of the query-lane scans are raw (x_c, x_ab, row) and are
+// scored here (RAW); the row-lane scan and the sample pass store final keys.
 template <int M, bool RAW, bool LUT>
 __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint64_t sm[];  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats
   __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kThreads / kWave];
-  __shared__ uint32_t off[kSelChunk + 1];
   __shared__ uint64_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
   __shared__ uint32_t total_s;
-  constexpr int PER = kSelChunk / kThreads;
+  constexpr int PER = kMaxSlabs / kThreads;  // slabs per thread
+  constexpr int CB = 4;                       // slot planes loaded as one batch
+  const int t = threadIdx.x;
   if (a.qovf[q]) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
-    if (threadIdx.x == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
     return;
   }
   float* lut_s = reinterpret_cast<float*>(sm + a.kpad + a.lds_keys);
   if (LUT)  // read after the barriers of the count below
-    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    for (int x = t; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
   const float* lut = LUT ? lut_s : a.t32;
+  // 1. slab counts: thread t owns slabs t, t + 256, ..., so every load of
+  // counts and of slot planes is one coalesced run per wave
   const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
-  // 1. candidate count
-  uint32_t part = 0;
-  for (int64_t i = threadIdx.x; i < a.n_slabs; i += kThreads) part += (uint32_t)sc[i];
-  const uint32_t incl0 = block_incl_scan(part, wsum);
-  if (threadIdx.x == kThreads - 1) total_s = incl0;
+  uint32_t cnt[PER], part = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = (int64_t)u * kThreads + t;
+    cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
+    part += cnt[u];
+  }
+  const uint32_t incl = block_incl_scan(part, wsum);
+  if (t == kThreads - 1) total_s = incl;
   __syncthreads();
   const int64_t ns = a.cnts[q];
   const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then n_slabs x scap slab slots
-  // Large candidate sets are compacted in place: entry j's destination is
-  // never after its source (a slab's count never exceeds its capacity, the
-  // sample's never exceeds S), so with every source of one step of 256 read
-  // before any destination of that step is written, nothing unread is
-  // overwritten. Small sets go to LDS.
-  const bool in_lds = n <= a.lds_keys;
-  uint64_t* keys = in_lds ? sm + a.kpad : region;
+  uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then the slot planes
+  const uint64_t* slots = region + a.S;
   const int32_t xq = a.popQ[q];
   const float Tq = a.t32[xq];
-  if (in_lds)
-    for (int64_t i = threadIdx.x; i < ns; i += kThreads) keys[i] = region[i];
-  const uint64_t* slots = region + a.S;
-  int64_t base = ns;
-  for (int64_t c0 = 0; c0 < a.n_slabs; c0 += kSelChunk) {
-    uint32_t cnt[PER], sum = 0;
+  auto key_of = [&](uint64_t e) { return RAW ? cand_key<M>(e, xq, Tq, lut, a) : e; };
+  auto slot = [&](uint32_t c, int u) { return slots[(size_t)c * a.n_slabs + (size_t)u * kThreads + t]; };
+  uint64_t* keys;
+  if (n <= a.lds_keys) {
+    // 2a. into LDS: each thread writes its slabs' entries at its offset in
+    // the count's scan; planes 0..CB-1 are loaded as one batch, deeper slots
+    // (rare) after
+    keys = sm + a.kpad;
+    for (int64_t i = t; i < ns; i += kThreads) keys[i] = region[i];
+    uint64_t v[CB][PER];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int u = 0; u < PER; ++u) v[c][u] = cnt[u] > (uint32_t)c ? slot(c, u) : 0;
+    uint32_t o = (uint32_t)ns + incl - part;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      const int64_t i = c0 + threadIdx.x * PER + u;
-      cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
-      sum += cnt[u];
-    }
-    const uint32_t incl = block_incl_scan(sum, wsum);
-    uint32_t o = incl - sum;
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      off[threadIdx.x * PER + u] = o;
+      for (int c = 0; c < CB; ++c)
+        if (cnt[u] > (uint32_t)c) keys[o + c] = key_of(v[c][u]);
+#pragma unroll 4
+      for (uint32_t c = CB; c < cnt[u]; ++c) keys[o + c] = key_of(slot(c, u));
       o += cnt[u];
     }
-    if (threadIdx.x == kThreads - 1) off[kSelChunk] = incl;
-    __syncthreads();
-    const uint32_t T = off[kSelChunk];
-    // every thread takes output positions j = t, t + 256, ... (four at a
-    // time, so their loads overlap) and finds the slab of j by binary search,
-    // so no thread walks a long slab alone
-    constexpr int R = 4;
-    for (uint32_t j0 = 0; j0 < T; j0 += kThreads * R) {
-      uint64_t v[R];
+  } else {
+    // 2b. in place, one slot plane at a time (keys in plane order). Plane
+    // c's keys go to [ns + E, ns + E + n_c) with E the entries of planes
+    // below c: E <= c * n_slabs and n_c <= n_slabs, so they stay below plane
+    // c + 1's sources, and every read of plane c comes before a write of it.
+    keys = region;
+    uint32_t cm = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t j = j0 + r * kThreads + threadIdx.x;
-        v[r] = 0;
-        if (j < T) {
-          int lo = 0, hi = kSelChunk - 1;  // largest slab s with off[s] <= j
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (off[mid] <= j) lo = mid;
-            else hi = mid - 1;
-          }
-          v[r] = slots[(size_t)(c0 + lo) * a.scap + (j - off[lo])];
-        }
-      }
+    for (int u = 0; u < PER; ++u) cm = cnt[u] > cm ? cnt[u] : cm;
+    const uint32_t cmax = block_max_u32(cm, wsum);
+    uint32_t E = (uint32_t)ns;
+    for (uint32_t c = 0; c < cmax; ++c) {
+      uint32_t m = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (RAW && j0 + r * kThreads + threadIdx.x < T) v[r] = cand_key<M>(v[r], xq, Tq, lut, a);
-      if (!in_lds) __syncthreads();  // block-uniform: every source of the step read before any write
+      for (int u = 0; u < PER; ++u) m += cnt[u] > c ? 1u : 0u;
+      const uint32_t pincl = block_incl_scan(m, wsum);
+      if (t == kThreads - 1) total_s = pincl;
+      uint64_t v[PER];
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t j = j0 + r * kThreads + threadIdx.x;
-        if (j < T) keys[base + j] = v[r];
-      }
+      for (int u = 0; u < PER; ++u) v[u] = cnt[u] > c ? slot(c, u) : 0;
+      __syncthreads();
+      uint32_t o = E + pincl - m;
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if (cnt[u] > c) keys[o++] = key_of(v[u]);
+      E += total_s;
     }
-    base += T;
-    __syncthreads();
   }
+  __syncthreads();
   select_and_write<M>(keys, n, q, a, sel, hist, wsum, &bprefix, &bneed, &nsel);
 }
 
