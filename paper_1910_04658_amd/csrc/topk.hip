@@ -246,51 +246,71 @@ __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* wsum) {
   return m;
 }
 
-// MSB-first radix select over 8-bit digits of the k largest of n keys
-// (1 <= k <= n). On return the k largest are exactly the keys with
-// (key & *pmask_out) >= prefix (the return value): either all digits were
-// resolved (then prefix is the k-th largest key itself) or, with `early`, the
-// digit bin holding the k-th key held exactly the keys still needed, so the
-// remaining digits need not be looked at. `keys` may point to LDS or global
-// memory. Block-wide call.
+// MSB-first radix select of the k largest of n keys (1 <= k <= n), in
+// digits of up to 8 bits from bit hb - 1 down to bit min_bit; every key has
+// the bits pmask0 (those at and above hb) equal to prefix0. On return the k
+// largest are exactly the keys with (key & *pmask_out) >= prefix (the return
+// value) when min_bit is 0: either every digit was resolved (prefix is then
+// the k-th largest key itself) or, with `early`, the bin holding the k-th
+// key held exactly the keys still needed. Digits below min_bit are not
+// resolved: the result is then the lower edge of the bin holding the k-th
+// key, a lower bound on it. `keys` may be in LDS or global memory; `hist`
+// holds 2 x 256 counters used in turn (the wave that scans one clears the
+// other), so a pass costs two block barriers. Block-wide call.
 template <typename K>
-__device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, uint32_t* wsum,
-                              K* bcast_prefix, int64_t* bcast_need, K* pmask_out = nullptr,
-                              bool early = false, int top_shift = (int)sizeof(K) * 8 - 8, K prefix0 = 0,
-                              K pmask0 = 0, int min_shift = 0) {
-  // (top_shift, prefix0, pmask0): every key has the bits pmask0 equal to
-  // prefix0, so the digits above top_shift need no pass. Digits below
-  // min_shift are not resolved: the result is then the lower edge of the
-  // bin holding the k-th key (a lower bound on it).
+__device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, K* bcast_prefix,
+                              int64_t* bcast_need, K* pmask_out, bool early, int hb, K prefix0, K pmask0,
+                              int min_bit) {
   __shared__ int done;
+  const int t = threadIdx.x;
   K prefix = prefix0, pmask = pmask0;
   int64_t need = k;
-  if (threadIdx.x == 0) done = 0;
-  for (int shift = top_shift; shift >= min_shift; shift -= 8) {
-    hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += kThreads) {
+  hist[t] = 0;
+  hist[kThreads + t] = 0;
+  if (t == 0) done = 0;
+  __syncthreads();
+  int buf = 0;
+  while (hb > min_bit) {
+    const int lo = hb - 8 > min_bit ? hb - 8 : min_bit;
+    const uint32_t dmask = (1u << (hb - lo)) - 1u;
+    uint32_t* h = hist + buf * kThreads;
+    for (int64_t i = t; i < n; i += kThreads) {
       const K key = keys[i];
-      if ((key & pmask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+      if ((key & pmask) == prefix) atomicAdd(&h[(uint32_t)(key >> lo) & dmask], 1u);
     }
     __syncthreads();
-    // thread t looks at bin 255 - t; inclusive scan = count of keys in bins >= 255 - t
-    const uint32_t b = 255u - threadIdx.x;
-    const uint32_t h = hist[b];
-    const uint32_t incl = block_incl_scan(h, wsum);
-    const uint32_t excl = incl - h;
-    if ((int64_t)excl < need && (int64_t)incl >= need) {
-      *bcast_prefix = prefix | ((K)b << shift);
-      *bcast_need = need - (int64_t)excl;
-      if (early && (int64_t)incl == need) done = 1;
+    if (t < kWave) {  // one wave scans the 256 bins from the top, four per lane
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = h[255 - 4 * t - j];
+        sum += c[j];
+      }
+      uint32_t incl = sum;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t o = __shfl_up(incl, off);
+        if (t >= off) incl += o;
+      }
+      uint32_t e = incl - sum;  // keys in the bins above this lane's
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if ((int64_t)e < need && (int64_t)(e + c[j]) >= need) {
+          *bcast_prefix = prefix | ((K)(uint32_t)(255 - 4 * t - j) << lo);
+          *bcast_need = need - (int64_t)e;
+          if (early && (int64_t)(e + c[j]) == need) done = 1;
+        }
+        e += c[j];
+        hist[(buf ^ 1) * kThreads + 4 * t + j] = 0;
+      }
     }
     __syncthreads();
     prefix = *bcast_prefix;
     need = *bcast_need;
-    pmask |= ((K)255) << shift;
-    const int stop = done;
-    __syncthreads();
-    if (stop) break;
+    pmask |= (K)dmask << lo;
+    if (done) break;  // block-uniform; set only before the barrier above
+    hb = lo;
+    buf ^= 1;
   }
   if (pmask_out) *pmask_out = pmask;
   return prefix;
@@ -635,8 +655,7 @@ __device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx,
 template <int M>
 __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint32_t keys[];  // [S]
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t wsum[kThreads / kWave];
+  __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
@@ -648,17 +667,17 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
     a.ovf[1] = 0;
   }
   __syncthreads();
-  // tau: the k-th best sample key to its top 24 bits, from the highest digit
-  // where the keys differ. The lower edge of its bin is a lower bound on it,
-  // which is all the filter needs: every row scoring at least tau becomes a
-  // candidate, and the final selection is exact.
+  // tau: the k-th best sample key resolved to the 16 bits below the highest
+  // bit where the keys differ. The lower edge of its bin is a lower bound on
+  // it, which is all the filter needs: every row scoring at least tau becomes
+  // a candidate, and the final selection is exact.
   uint64_t klo, khi;
   block_key_range(keys, a.S, &klo, &khi);
   const uint32_t diff = (uint32_t)(klo ^ khi);
-  const int top = diff ? (31 - __clz((int)diff)) / 8 * 8 : 0;
-  const uint32_t pmask0 = top + 8 >= 32 ? 0u : ~((1u << (top + 8)) - 1u);
-  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, wsum, &bprefix, &bneed, nullptr, true,
-                                                      top, (uint32_t)khi & pmask0, pmask0, top < 8 ? top : 8);
+  const int hb = diff ? 32 - __clz((int)diff) : 0;
+  const uint32_t pmask0 = hb >= 32 ? 0u : ~((1u << hb) - 1u);
+  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, &bprefix, &bneed, nullptr, true, hb,
+                                                      (uint32_t)khi & pmask0, pmask0, hb > 16 ? hb - 16 : 0);
   uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     if (keys[i] >= tau_key) {
@@ -697,23 +716,46 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
   QConst k = {};
   const bool q_ok = qi < a.nQ;
   if (q_ok) k = a.qc[qi];
-  for (int r = threadIdx.x / kWave; r < kBoundX; r += kThreads / kWave) {
-    const int xc = (int)by * kBoundX + r;
+  constexpr int RW = kThreads / kWave;
+  constexpr int RPT = kBoundX / RW;  // table rows per thread
+  const int wid = threadIdx.x / kWave;
+  float bnd[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int xc = (int)by * kBoundX + wid + r * RW;
+    const float Tc = lut[xc < a.N ? xc : a.N];
+    float bound = fmaf(k.Tq + Tc, k.A, k.C);
+    if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
+    bnd[r] = bound;
+  }
+  // X = max{x in [0, N] : T(x) <= bound} (T non-decreasing), or -1, for the
+  // thread's rows at once: a search whose steps depend only on N (so every
+  // row and lane takes the same steps and every read is inside the table),
+  // each step issuing one table read per row before using any
+  int base[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) base[r] = 0;
+  for (int len = a.N + 1; len > 1;) {  // the count of x <= X lies in [base, base + len]
+    const int half = len >> 1;
+    float tv[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) tv[r] = lut[base[r] + half];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) base[r] = tv[r] <= bnd[r] ? base[r] + half : base[r];
+    len -= half;
+  }
+  float tv[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) tv[r] = lut[base[r]];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int xc = (int)by * kBoundX + wid + r * RW;
     if (xc > a.N) break;
     uint16_t m = 65535;
     if (q_ok) {
-      const float Tc = lut[xc];
-      const float s = k.Tq + Tc;
-      float bound = fmaf(s, k.A, k.C);
-      if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
-      // largest x in [0, N] with T(x) <= bound (T non-decreasing), or -1
-      int lo = -1, hi = a.N;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (lut[mid] <= bound) lo = mid;
-        else hi = mid - 1;
-      }
-      const int64_t mm = (int64_t)k.xq + xc - lo;
+      const int X = base[r] + (tv[r] <= bnd[r] ? 1 : 0) - 1;
+      const int64_t mm = (int64_t)k.xq + xc - X;
       m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
     }
     a.mtab[(size_t)xc * a.nQp + qi] = m;
@@ -1082,18 +1124,18 @@ __device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
 
 template <int M>
 __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a,
-                                 uint64_t* sel, uint32_t* hist, uint32_t* wsum, uint64_t* bprefix,
-                                 int64_t* bneed, uint32_t* nsel) {
+                                 uint64_t* sel, uint32_t* hist, uint64_t* bprefix, int64_t* bneed,
+                                 uint32_t* nsel) {
   // the highest digit in which the keys differ: the bits above it are common
   // to every key, so the radix select starts there
   uint64_t lo, hi;
   block_key_range(keys, n, &lo, &hi);
   const uint64_t diff = lo ^ hi;
-  const int top = diff ? (63 - __clzll((long long)diff)) / 8 * 8 : 0;
-  const uint64_t pmask0 = top + 8 >= 64 ? 0 : ~((((uint64_t)1) << (top + 8)) - 1);
+  const int hb = diff ? 64 - __clzll((long long)diff) : 0;
+  const uint64_t pmask0 = hb >= 64 ? 0 : ~((((uint64_t)1) << hb) - 1);
   uint64_t pmask = 0;
   const uint64_t kth =
-      radix_select_kth<uint64_t>(keys, n, a.k, hist, wsum, bprefix, bneed, &pmask, true, top, hi & pmask0, pmask0);
+      radix_select_kth<uint64_t>(keys, n, a.k, hist, bprefix, bneed, &pmask, true, hb, hi & pmask0, pmask0, 0);
   if (threadIdx.x == 0) *nsel = 0;
   for (int t = threadIdx.x; t < a.kpad; t += kThreads) sel[t] = 0;
   __syncthreads();
@@ -1133,7 +1175,7 @@ __device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, c
 template <int M, bool RAW, bool LUT>
 __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint64_t sm[];  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats
-  __shared__ uint32_t hist[256];
+  __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint64_t bprefix;
   __shared__ int64_t bneed;
@@ -1223,15 +1265,14 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     }
   }
   __syncthreads();
-  select_and_write<M>(keys, n, q, a, sel, hist, wsum, &bprefix, &bneed, &nsel);
+  select_and_write<M>(keys, n, q, a, sel, hist, &bprefix, &bneed, &nsel);
 }
 
 // ---- fallback: whole-corpus selection for overflowed queries ----------------
 template <int M>
 __device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int64_t nb) {
   extern __shared__ uint64_t sm[];  // sel[kpad], then qw[W64]
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t wsum[kThreads / kWave];
+  __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint64_t bprefix;
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
@@ -1254,7 +1295,7 @@ __device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int6
       keys[i] = make_key<M>(sc, (uint32_t)i);
     }
     __syncthreads();
-    select_and_write<M>(keys, a.nC, q, a, sel, hist, wsum, &bprefix, &bneed, &nsel);
+    select_and_write<M>(keys, a.nC, q, a, sel, hist, &bprefix, &bneed, &nsel);
   }
 }
 
