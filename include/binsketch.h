@@ -324,6 +324,17 @@ int bs_timing_get(const char* name, double* total_ms, int64_t* count);
  */
 int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys);
 
+/*
+ * Testing hook, not for production callers: bs_topk takes its filter
+ * threshold tau as the `rank`-th best sample score when that is below the
+ * automatic rank (1 makes tau the best sample score, so most queries fail the
+ * select's check that at least k candidates score >= tau and are ranked by
+ * the whole-corpus fallback). A rank below 1 restores the automatic choice.
+ * Lets tests drive the fallback on a failed check, which must return the same
+ * result. Process-wide; not thread-safe. Returns 0.
+ */
+int bs_debug_set_topk_tau_rank(int64_t rank);
+
 #ifdef __cplusplus
 }
 #endif

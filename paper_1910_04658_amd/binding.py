@@ -105,6 +105,8 @@ def load():
             L.bs_mlp_to_bf16.restype = ctypes.c_int
             L.bs_debug_set_topk_limits.argtypes = [i64, i64]
             L.bs_debug_set_topk_limits.restype = ctypes.c_int
+            L.bs_debug_set_topk_tau_rank.argtypes = [i64]
+            L.bs_debug_set_topk_tau_rank.restype = ctypes.c_int
             BI, BSh = ctypes.POINTER(BatchItem), ctypes.POINTER(BatchShape)
             L.bs_batch_workspace_size.argtypes = [BI, i32]
             L.bs_batch_workspace_size.restype = sz
@@ -308,6 +310,12 @@ def debug_set_topk_limits(slab_capacity: int = -1, lds_keys: int = -1):
     """Test hook: shrink the top-k candidate slots per slab / the LDS key
     buffer of the select (-1 = automatic)."""
     load().bs_debug_set_topk_limits(int(slab_capacity), int(lds_keys))
+
+
+def debug_set_topk_tau_rank(rank: int = -1):
+    """Test hook: take the filter threshold as the rank-th best sample score
+    (below the automatic rank; -1 = automatic)."""
+    load().bs_debug_set_topk_tau_rank(int(rank))
 
 
 def timing_enable(on: bool = True):

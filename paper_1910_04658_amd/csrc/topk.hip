@@ -9,10 +9,13 @@
 //
 // Selection without a global sort, in three launches plus a rare fallback:
 //  1. sample: per query (one block), score a strided sample of S corpus rows,
-//     find the k-th best score tau among them by an LDS radix select, append
+//     find the kt-th best score tau among them by an LDS radix select, append
 //     the sample rows scoring >= tau to the query's candidate list, and store
-//     per-query constants for the filter below. The k-th best over the whole
-//     corpus is >= tau, so every true top-k row scores >= tau.
+//     per-query constants for the filter below. kt <= k is the smallest rank
+//     at which more than kt - 1 sample rows beat the true k-th best row with
+//     probability below 1e-9 (a Poisson tail; kt = k when the sample is the
+//     corpus), so tau is almost always <= the true k-th best score and the
+//     candidates are about kt * nC / S rather than k * nC / S.
 //  2. scan: every other (query, corpus row) pair. Lanes hold queries (words in
 //     VGPRs), corpus rows arrive on the scalar unit. Instead of evaluating the
 //     score (an IEEE division per pair) the kernel tests x_ab >= m[x_c][q], a
@@ -22,11 +25,13 @@
 //  3. select: per query, the sample and slab candidates are compacted (block
 //     scan over slab counts), scored exactly as unique 64-bit keys (score
 //     key, then inverted index), the k-th key found by radix select and the
-//     k winners sorted (bitonic).
-//  4. fallback: a query with more survivors in one slab than its slot range
-//     holds (e.g. massive exact ties) is recomputed over the whole corpus by a
-//     few blocks and selected the same way. Results never depend on which path
-//     ran.
+//     k winners sorted (bitonic). Before that, tau is verified: with at least
+//     k candidates scoring >= tau, the true k-th best score is >= tau, and
+//     every row scoring >= tau is a candidate, so the selection is exact.
+//  4. fallback: a query that fails that check, or has more survivors in one
+//     slab than its slot range holds (e.g. massive exact ties), is recomputed
+//     over the whole corpus by a few blocks and selected the same way. Results
+//     never depend on which path ran.
 #include <float.h>
 #include <string.h>
 
@@ -58,15 +63,17 @@ constexpr int kSplitRows = 16;       // rows per partial-count exchange of the w
 constexpr int kFallbackBlocks = 16;
 
 struct QConst {  // per-query constants written by the sample pass
-  float tau;     // k-th best sample score
+  float tau;     // (a lower bound on) the kt-th best sample score
   float Tq;      // T(|q_s|)
   float A, B, C; // filter bound: T(x_u) <= fma(sqrtTc, B, fma(s, A, C))
   int32_t xq;    // |q_s|
-  int32_t pad0, pad1;
+  uint32_t tau_key;  // tau as a selection key
+  int32_t pad1;
 };
 
 struct Plan {
   int64_t S, stride, F;
+  int64_t kt;  // rank of tau in the sample
   int64_t qpl, ngrp, nqb4, n_slabs, slab, scap, kmax;  // scan geometry
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
@@ -85,6 +92,25 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   S = S < kSampleMin ? kSampleMin : (S > kSampleMax ? kSampleMax : S);
   p.S = nC < S ? nC : S;
   p.stride = p.S > 0 ? nC / p.S : 1;
+  // tau's rank kt in the sample: the number of sample rows better than the
+  // true k-th best row is about Poisson(lambda), lambda = (k - 1) S / nC, and
+  // kt is the smallest rank with P(X >= kt) < 1e-9 (at most k; k when the
+  // sample is the whole corpus or lambda is too large to evaluate)
+  p.kt = k;
+  if (p.S < nC) {
+    const double lam = (double)(k - 1) * (double)p.S / (double)nC;
+    double pmf = exp(-lam), cdf = pmf;
+    int64_t r = 1;
+    if (pmf > 0.0)
+      while (r < k && 1.0 - cdf >= 1e-9) {
+        pmf *= lam / (double)r;
+        cdf += pmf;
+        ++r;
+      }
+    else
+      r = k;
+    p.kt = r;
+  }
   // scan geometry: waves of QPL x 64 queries, four per block, ~16k waves
   const int W32 = N / 32;
   const bool pow2 = (W32 & (W32 - 1)) == 0;
@@ -135,7 +161,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // (a slot slab of the word-split scan is one wave's quarter of a row slab)
   const int64_t slot_rows = p.split ? (p.slab + kSplitWaves - 1) / kSplitWaves : p.slab;
   if (p.split) p.n_slabs *= kSplitWaves;
-  const double e = p.S > 0 ? (double)slot_rows * k / (double)p.S : 0.0;
+  const double e = p.S > 0 ? (double)slot_rows * (double)p.kt / (double)p.S : 0.0;
   int64_t scap = (int64_t)ceil(2.0 * e + 6.0 * sqrt(e)) + 8;
   p.scap = scap < slot_rows ? scap : slot_rows;
   if (p.S >= nC) {  // the sample covers the corpus: no scan, no slabs
@@ -157,7 +183,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // k = 100 (a query with more candidates selects in place in its candidate
   // region), and T when the kernel scores raw survivors, all within 60 KB
   {
-    const double expect = p.S > 0 ? (double)k * (double)nC / (double)p.S : 0.0;
+    const double expect = p.S > 0 ? (double)p.kt * (double)nC / (double)p.S : 0.0;
     int64_t lk = ((int64_t)(1.25 * expect) + 512 + 255) / 256 * 256;
     p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
     int64_t kpad = 1;
@@ -417,6 +443,7 @@ struct TopkArgs {
   int64_t s_rblocks, s_nqb, s_qb;  // sample-score grid: row blocks x query blocks of s_qb queries
   int64_t F;                       // fallback blocks
   int32_t N, W32, k, kpad;
+  int32_t kt;                      // rank of tau in the sample (<= k)
   int32_t qpl, rows, split;        // scan variant: queries per lane, row-lane scan, word-split scan
   int32_t sel_lut;                 // the select keeps T in LDS
 };
@@ -462,6 +489,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.W32 = c->W32;
   a.k = c->k;
   a.kpad = c->kpad;
+  a.kt = c->kt;
   a.qpl = c->qpl;
   a.rows = c->rows;
   a.split = c->split;
@@ -490,7 +518,8 @@ __device__ QConst make_qconst(float tau, float Tq, int32_t xq) {
   c.tau = tau;
   c.Tq = Tq;
   c.xq = xq;
-  c.pad0 = c.pad1 = 0;
+  c.tau_key = 0;
+  c.pad1 = 0;
   const float at = fabsf(tau);
   if (M == BS_JACCARD) {
     // js >= tau  =>  T_u <= s / (1 + tau - delta)
@@ -676,7 +705,7 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
   const uint32_t diff = (uint32_t)(klo ^ khi);
   const int hb = diff ? 32 - __clz((int)diff) : 0;
   const uint32_t pmask0 = hb >= 32 ? 0u : ~((1u << hb) - 1u);
-  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.k, hist, &bprefix, &bneed, nullptr, true, hb,
+  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.kt, hist, &bprefix, &bneed, nullptr, true, hb,
                                                       (uint32_t)khi & pmask0, pmask0, hb > 16 ? hb - 16 : 0);
   uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
@@ -690,7 +719,9 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
     const int32_t xq = a.popQ[q];
     a.cnts[q] = (int32_t)nsel;
     a.qovf[q] = 0;
-    a.qc[q] = make_qconst<M>(key_score<M>(tau_key), a.t32[xq], xq);
+    QConst c = make_qconst<M>(key_score<M>(tau_key), a.t32[xq], xq);
+    c.tau_key = tau_key;
+    a.qc[q] = c;
   }
 }
 
@@ -1265,6 +1296,20 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     }
   }
   __syncthreads();
+  if (a.kt < a.k) {
+    // tau check: with at least k candidates scoring >= tau the true k-th
+    // best score is >= tau, and every row scoring >= tau is a candidate
+    const uint64_t thr = (uint64_t)a.qc[q].tau_key << 32;
+    uint32_t m = 0;
+    for (int64_t i = t; i < n; i += kThreads) m += keys[i] >= thr ? 1u : 0u;
+    const uint32_t above = block_incl_scan(m, wsum);
+    if (t == kThreads - 1) total_s = above;
+    __syncthreads();
+    if (total_s < (uint32_t)a.k) {  // block-uniform: the whole-corpus fallback ranks the query
+      if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+      return;
+    }
+  }
   select_and_write<M>(keys, n, q, a, sel, hist, &bprefix, &bneed, &nsel);
 }
 
@@ -1563,6 +1608,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.N = it.N;
   a.W32 = it.N / 32;
   a.k = it.k;
+  a.kt = (int32_t)p.kt;
   int kpad = 1;
   while (kpad < it.k) kpad <<= 1;
   a.kpad = kpad;
@@ -1577,6 +1623,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
 // Overrides for tests of the overflow paths (negative = automatic).
 static int64_t g_scap_override = -1;
 static int64_t g_ldskeys_override = -1;
+static int64_t g_taurank_override = -1;
 
 // ---- group plans ----------------------------------------------------------------
 struct TopkGroup {
@@ -1749,6 +1796,11 @@ extern "C" int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys)
   return 0;
 }
 
+extern "C" int bs_debug_set_topk_tau_rank(int64_t rank) {
+  bs::g_taurank_override = rank < 1 ? -1 : rank;
+  return 0;
+}
+
 extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint64_t* C,
                              const int32_t* popC, int64_t nC, int32_t N, int32_t measure, int32_t k,
                              int32_t* out_idx, float* out_score, void* workspace, size_t workspace_bytes,
@@ -1770,6 +1822,7 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
     p.kmax = p.S + p.n_slabs * p.scap;
   }
   if (g_ldskeys_override >= 0 && g_ldskeys_override < p.lds_keys) p.lds_keys = g_ldskeys_override;
+  if (g_taurank_override >= 1 && g_taurank_override < p.kt) p.kt = g_taurank_override;
   char* ws = static_cast<char*>(workspace);
   TopkItem it;
   it.Q = Q;

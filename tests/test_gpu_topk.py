@@ -88,6 +88,28 @@ def test_overflow_fallback_path(m, nq, dev):
         assert_topk_equal(gi, gs, oi, osc)
 
 
+@pytest.mark.parametrize("m", [oracle.JS, oracle.COS])
+@pytest.mark.parametrize("nq", [9, 70])
+def test_failed_tau_check_falls_back(m, nq, dev):
+    """The filter threshold is the sample's kt-th best score with kt < k; the
+    select checks that at least k candidates reach it. Forcing kt down to 1
+    or 5 makes the check fail for most queries, which then go to the
+    whole-corpus fallback; the result must not change (both scan modes)."""
+    from paper_1910_04658_amd import binding as bs
+    c = _mid("c30k", lambda: datagen.lognormal_corpus(30000, d=40000, seed=27))
+    w, S = sketch_both(c, 512, 11, dev)
+    q = np.linspace(0, 29999, nq).astype(np.int64)
+    sel = np.arange(0, nq, max(1, nq // 9))
+    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, 512, m, 40)
+    for rank in (1, 5, -1):
+        try:
+            bs.debug_set_topk_tau_rank(rank)
+            gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 512, m, 40)
+        finally:
+            bs.debug_set_topk_tau_rank()
+        assert_topk_equal(gi[sel], gs[sel], oi, osc)
+
+
 @pytest.mark.parametrize("lds_keys", [None, 0, 1024])
 @pytest.mark.parametrize("nq", [9, 70])
 def test_large_candidate_sets_compact_in_place(lds_keys, nq, dev):
