@@ -485,7 +485,8 @@ def main():
     value = pairs / (ms / 1e3)
 
     def scan_roofline(N, kt):
-        S = min(nC, 4096)
+        from paper_1910_04658_amd import binding as bs
+        S = bs.topk_sample_size(nC)  # rows scored by the sample pass, not the scan
         if "topk_scan" not in kt:
             return None
         ops = nQ * (nC - S) * (N // 16)  # one AND and one popcount per 32-bit word pair

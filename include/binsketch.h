@@ -160,6 +160,13 @@ bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const 
  * The result does not depend on the launch configuration or on timing.
  */
 size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int32_t k);
+
+/*
+ * Corpus rows that bs_topk scores exactly in its sample pass for a corpus of
+ * nC rows (every stride-th row, stride = nC / S); the scan pass estimates the
+ * other nC - S rows of every query. 0 for nC < 1. Pure function of nC.
+ */
+int64_t bs_topk_sample_size(int64_t nC);
 bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint64_t* C,
                   const int32_t* popC, int64_t nC, int32_t N, int32_t measure, int32_t k,
                   int32_t* out_idx, float* out_score, void* workspace, size_t workspace_bytes,

@@ -81,6 +81,8 @@ def load():
             L.bs_estimate.restype = ctypes.c_int
             L.bs_topk_workspace_size.argtypes = [i64, i64, i32, i32]
             L.bs_topk_workspace_size.restype = sz
+            L.bs_topk_sample_size.argtypes = [i64]
+            L.bs_topk_sample_size.restype = i64
             L.bs_topk.argtypes = [p, p, i64, p, p, i64, i32, i32, i32, p, p, p, sz, p]
             L.bs_topk.restype = ctypes.c_int
             L.bs_timing_enable.argtypes = [ctypes.c_int]
@@ -273,6 +275,11 @@ def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "j
 
 def topk_workspace_size(nQ: int, nC: int, N: int, k: int) -> int:
     return int(load().bs_topk_workspace_size(int(nQ), int(nC), int(N), int(k)))
+
+
+def topk_sample_size(nC: int) -> int:
+    """Corpus rows bs_topk scores exactly in its sample pass."""
+    return int(load().bs_topk_sample_size(int(nC)))
 
 
 def topk(Q: torch.Tensor, C: torch.Tensor, N: int, measure, k: int, scores: bool = True,

@@ -50,7 +50,7 @@ void launch_row_popcount(const uint64_t* X, int64_t n, int32_t N, int32_t* pop, 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSampleMin = 4096;     // rows scored in the sample pass
+constexpr int kSampleMin = 2048;     // rows scored in the sample pass
 constexpr int kSampleMax = 15360;  // keys fit 60 KB of LDS in the sample select
 constexpr int kSelectLdsKeys = 6144; // candidate keys selected in LDS (else in a global buffer)
 constexpr int kMaxSlabs = 2048;      // slot slabs per query at most (the select reads every count at once)
@@ -84,13 +84,17 @@ struct Plan {
       off_scratch, off_mtab, off_ovf, off_skeys, total;
 };
 
-Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tune) {
-  Plan p;
-  // sample size: 4,096 rows, growing as nC/256 up to 15,360 for large corpora
-  // (the candidate count per query is about k * nC / S)
+// Sample size: 2,048 rows, growing as nC/256 up to 15,360 for large corpora
+// (the candidate count per query is about kt * nC / S), at most nC.
+int64_t sample_rows(int64_t nC) {
   int64_t S = nC / 256;
   S = S < kSampleMin ? kSampleMin : (S > kSampleMax ? kSampleMax : S);
-  p.S = nC < S ? nC : S;
+  return nC < S ? nC : S;
+}
+
+Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tune) {
+  Plan p;
+  p.S = sample_rows(nC);
   p.stride = p.S > 0 ? nC / p.S : 1;
   // tau's rank kt in the sample: the number of sample rows better than the
   // true k-th best row is about Poisson(lambda), lambda = (k - 1) S / nC, and
@@ -1795,6 +1799,8 @@ extern "C" int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys)
   bs::g_ldskeys_override = lds_keys < 0 ? -1 : lds_keys;
   return 0;
 }
+
+extern "C" int64_t bs_topk_sample_size(int64_t nC) { return nC < 1 ? 0 : bs::sample_rows(nC); }
 
 extern "C" int bs_debug_set_topk_tau_rank(int64_t rank) {
   bs::g_taurank_override = rank < 1 ? -1 : rank;

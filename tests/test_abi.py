@@ -136,3 +136,14 @@ def test_batch_rejects_bad_arguments(lib):
     assert lib.bs_batch_shapes(None, None, 0) == 0
     assert lib.bs_batch_graph_nodes(None) == 0
     lib.bs_batch_destroy(None)
+
+
+def test_topk_sample_size(lib):
+    """Rows the sample pass scores exactly: the whole corpus while it has at
+    most 2,048 rows, then 2,048 up to nC / 256, growing as nC / 256 up to
+    15,360 rows."""
+    f = lib.bs_topk_sample_size
+    assert f(0) == 0 and f(1) == 1 and f(2048) == 2048
+    assert f(2049) == 2048 and f(100_000) == 2048
+    assert f(600_000) == 600_000 // 256
+    assert f(15360 * 256) == 15360 and f(10**9) == 15360
