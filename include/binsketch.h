@@ -106,6 +106,35 @@ bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_row
                     size_t workspace_bytes, void* stream);
 
 /*
+ * bs_sketch_parts — bs_sketch of up to BS_SKETCH_MAX_PARTS CSR matrices that
+ * share one map pi (e.g. a corpus and its queries) in one launch: the map is
+ * packed and staged once, and the waves are split between the parts in
+ * proportion to their set bits. Every part's sketches and popcounts are
+ * exactly what bs_sketch writes for it alone.
+ *
+ *   parts      host array of n_parts descriptions; each field as the
+ *              bs_sketch argument of the same name (device pointers).
+ *   n_parts    1 .. BS_SKETCH_MAX_PARTS.
+ *   pi, d, N, err_flag, workspace, workspace_bytes, stream: as bs_sketch
+ *              (one err_flag for the call; flags of every part are ORed in).
+ * Returns BS_ERR_ARG for n_parts out of range or any bad size or width (as
+ * bs_sketch, for every part), then BS_ERR_NULL for a NULL parts array or
+ * pi, or a part's NULL pointer that bs_sketch would reject.
+ */
+#define BS_SKETCH_MAX_PARTS 4
+typedef struct {
+  const int32_t* indptr;  /* int32[n_rows + 1] */
+  const int32_t* indices; /* int32[nnz] */
+  int64_t n_rows;
+  int64_t nnz;
+  uint64_t* sketches;     /* uint64[n_rows][N/64] */
+  int32_t* popcounts;     /* int32[n_rows] or NULL */
+} bs_sketch_part;
+bs_status bs_sketch_parts(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi, int64_t d,
+                          int32_t N, int32_t* err_flag, void* workspace, size_t workspace_bytes,
+                          void* stream);
+
+/*
  * bs_and_popcount — all-pairs sketch inner products
  * out[p][q] = |A_p AND B_q| = <a_s, b_s> (Algorithm 1, second step).
  *

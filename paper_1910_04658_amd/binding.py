@@ -29,6 +29,13 @@ _lock = threading.Lock()
 _lib = None
 
 
+class SketchPart(ctypes.Structure):
+    """bs_sketch_part (field order and types as in binsketch.h)."""
+    _fields_ = [("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
+                ("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("sketches", ctypes.c_void_p), ("popcounts", ctypes.c_void_p)]
+
+
 class BatchItem(ctypes.Structure):
     """bs_batch_item (field order and types as in binsketch.h)."""
     _fields_ = [("indptr", ctypes.c_void_p), ("indices", ctypes.c_void_p),
@@ -70,6 +77,8 @@ def load():
             L.bs_words.argtypes = [i32]
             L.bs_words.restype = i32
             L.bs_sketch.argtypes = [p, p, i64, i64, p, i64, i32, p, p, p, p, sz, p]
+            L.bs_sketch_parts.argtypes = [ctypes.POINTER(SketchPart), i32, p, i64, i32, p, p, sz, p]
+            L.bs_sketch_parts.restype = ctypes.c_int
             L.bs_sketch_workspace_size.argtypes = [i64, i32]
             L.bs_sketch_workspace_size.restype = sz
             L.bs_sketch.restype = ctypes.c_int
@@ -217,6 +226,58 @@ def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int
                           _ptr(workspace), wsn, _stream())
     _check(st, "bs_sketch")
     return out, pop
+
+
+MAX_PARTS = 4  # BS_SKETCH_MAX_PARTS
+
+
+def sketch_parts(parts, pi: torch.Tensor, N: int, outs=None, popcounts=None,
+                 err_flag: torch.Tensor | None = None, workspace: torch.Tensor | None | bool = True):
+    """bs_sketch_parts: the (indptr, indices) CSR matrices of `parts` (at most
+    four) sketched with one map in one launch. outs / popcounts: optional
+    lists of preallocated outputs (a None popcounts entry skips that part's
+    counts). Returns [(sketches, popcounts), ...], each as sketch() would."""
+    if not 1 <= len(parts) <= MAX_PARTS:
+        raise ValueError("1 to %d parts" % MAX_PARTS)
+    _need(pi, "pi", torch.int32, 1)
+    W = words(N)
+    if W == 0:
+        raise ValueError("invalid sketch width N=%d" % N)
+    arr = (SketchPart * len(parts))()
+    res = []
+    for i, (indptr, indices) in enumerate(parts):
+        _need(indptr, "indptr", torch.int32, 1)
+        _need(indices, "indices", torch.int32, 1)
+        n = indptr.numel() - 1
+        if n < 0:
+            raise ValueError("indptr must hold n_rows + 1 entries")
+        out = outs[i] if outs is not None else torch.empty((n, W), dtype=torch.int64, device=indptr.device)
+        _need(out, "out", torch.int64, 2)
+        if tuple(out.shape) != (n, W):
+            raise ValueError("out must be [n_rows][N/64]")
+        if popcounts is None:
+            pop = torch.empty(n, dtype=torch.int32, device=indptr.device)
+        else:
+            pop = popcounts[i]
+            if pop is not None:
+                _need(pop, "popcounts", torch.int32, 1)
+                if pop.numel() != n:
+                    raise ValueError("popcounts must have n_rows entries")
+        arr[i] = SketchPart(_ptr(indptr), _ptr(indices if indices.numel() else None), n, indices.numel(),
+                            _ptr(out), _ptr(pop))
+        res.append((out, pop))
+    if err_flag is not None:
+        _need(err_flag, "err_flag", torch.int32)
+    if workspace is True:
+        need = sketch_workspace_size(max(pi.numel(), 1), N)
+        workspace = _workspace(need, pi.device) if need else None
+    elif workspace is False:
+        workspace = None
+    wsn = workspace.numel() if workspace is not None else 0
+    st = load().bs_sketch_parts(arr, len(parts), _ptr(pi), pi.numel(), int(N), _ptr(err_flag),
+                                _ptr(workspace), wsn, _stream())
+    _check(st, "bs_sketch_parts")
+    return res
 
 
 def and_popcount(A: torch.Tensor, B: torch.Tensor, N: int, out: torch.Tensor | None = None):

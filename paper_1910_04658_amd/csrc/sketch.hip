@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kWavesPerBlock * kWave) void sketch_group_kernel(co
 // Each wave then owns a contiguous range of rows, processed in windows of G
 // rows exactly as above.
 constexpr int kBigBlockWaves = 16;
+constexpr int kMaxParts = BS_SKETCH_MAX_PARTS;  // CSR matrices sketched by one launch
 constexpr int kUnrollLds = 16;  // element loads in flight per lane
 
 // LDS byte addresses as plain integers, so that an address is one
@@ -283,7 +284,9 @@ __device__ __forceinline__ uint32_t lds_addr(const uint32_t* p) {
 __device__ __forceinline__ lds_u32* lds_ptr(uint32_t a) { return (lds_u32*)(uintptr_t)a; }
 
 struct SketchLdsArgs {
-  SketchArgs s;
+  SketchArgs s[kMaxParts];  // the CSR matrices (parts) of the call; one map, one width
+  int32_t n_parts;
+  int32_t wave_off[kMaxParts + 1];  // part i is sketched by waves [wave_off[i], wave_off[i + 1])
   const uint32_t* __restrict__ packed;  // bit-packed map (table_words - 1 words)
   int32_t bits;         // bits per packed map entry
   int32_t table_words;  // packed map words in LDS (including one pad word)
@@ -339,7 +342,6 @@ __global__ void pack_map_kernel(const int32_t* __restrict__ pi, int64_t d, int32
 
 __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(SketchLdsArgs A) {
   extern __shared__ uint32_t lds[];
-  const SketchArgs& a = A.s;
   const int bits = A.bits;
   uint32_t* table = lds;
   uint32_t* stage_base = lds + A.table_words;
@@ -375,9 +377,22 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   }
   __syncthreads();
 
-  // 2. each wave owns a contiguous range of rows, in windows of G rows
+  // 2. each wave owns a contiguous range of rows of one part, in windows of G
+  // rows. The part is picked by constant-index selects (no dynamic indexing
+  // of the argument block).
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
+  const int64_t gwv = (int64_t)blockIdx.x * kBigBlockWaves + wid;
+  SketchArgs a = A.s[0];
+  int64_t w_lo = 0, w_hi = A.wave_off[1];
+#pragma unroll
+  for (int i = 1; i < kMaxParts; ++i) {
+    if (i < A.n_parts && gwv >= A.wave_off[i]) {
+      a = A.s[i];
+      w_lo = A.wave_off[i];
+      w_hi = A.wave_off[i + 1];
+    }
+  }
   const int W32 = a.W32;
   uint32_t* sk = stage_base + (size_t)wid * a.stride;
   uint32_t* cnt = sk + (size_t)a.G * W32;
@@ -388,8 +403,8 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   // With a monotone indptr the ranges partition the rows; a range whose end
   // comes before its start can only come from a malformed indptr and is
   // reported.
-  const int64_t total_waves = (int64_t)gridDim.x * kBigBlockWaves;
-  const int64_t wv = (int64_t)blockIdx.x * kBigBlockWaves + wid;
+  const int64_t total_waves = w_hi - w_lo;  // waves of this part
+  const int64_t wv = gwv - w_lo;
   int64_t rw0, rw1;
   {
     const int half = lane >> 5, hl = lane & 31;
@@ -749,17 +764,75 @@ extern "C" size_t bs_sketch_workspace_size(int64_t d, int32_t N) {
   return align256((size_t)map_table_words(d, N) * 4);
 }
 
-extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_rows,
-                               int64_t nnz, const int32_t* pi, int64_t d, int32_t N,
-                               uint64_t* sketches, int32_t* popcounts, int32_t* err_flag,
-                               void* workspace, size_t workspace_bytes, void* stream) {
-  using namespace bs;
-  if (n_rows < 0 || nnz < 0 || nnz > INT32_MAX || d < 1 || d > INT32_MAX || !valid_width(N))
-    return BS_ERR_ARG;
-  if (!indptr || !pi || (!indices && nnz > 0) || (!sketches && n_rows > 0)) return BS_ERR_NULL;
+namespace bs {
+namespace {
+
+// Waves per part in proportion to its set bits plus rows; a part with rows
+// always gets at least one. wave_off[i] is the first wave of part i.
+void split_waves(const bs_sketch_part* parts, int32_t n_parts, int64_t total, int32_t* wave_off) {
+  int64_t wt[kMaxParts] = {}, w[kMaxParts] = {}, wsum = 0, used = 0;
+  for (int i = 0; i < n_parts; ++i) {
+    wt[i] = parts[i].n_rows > 0 ? parts[i].nnz + parts[i].n_rows : 0;
+    wsum += wt[i];
+  }
+  for (int i = 0; i < n_parts; ++i) {
+    if (wt[i] == 0) continue;
+    w[i] = total * wt[i] / wsum;
+    if (w[i] < 1) w[i] = 1;
+    used += w[i];
+  }
+  while (used > total) {  // total >= the parts with rows, so a part with two or more waves exists
+    int j = -1;
+    for (int i = 0; i < n_parts; ++i)
+      if (w[i] > 1 && (j < 0 || w[i] > w[j])) j = i;
+    --w[j];
+    --used;
+  }
+  while (used < total) {  // the rest to the parts with the most weight per wave
+    int j = -1;
+    for (int i = 0; i < n_parts; ++i)
+      if (wt[i] > 0 && (j < 0 || wt[i] * w[j] > wt[j] * w[i])) j = i;
+    ++w[j];
+    ++used;
+  }
+  wave_off[0] = 0;
+  for (int i = 0; i < kMaxParts; ++i) wave_off[i + 1] = wave_off[i] + (int32_t)(i < n_parts ? w[i] : 0);
+}
+
+bs_status sketch_parts_impl(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi, int64_t d, int32_t N,
+                            int32_t* err_flag, void* workspace, size_t workspace_bytes, void* stream) {
+  if (n_parts < 1 || n_parts > kMaxParts || d < 1 || d > INT32_MAX || !valid_width(N)) return BS_ERR_ARG;
+  if (!parts) return BS_ERR_NULL;
+  for (int i = 0; i < n_parts; ++i)
+    if (parts[i].n_rows < 0 || parts[i].nnz < 0 || parts[i].nnz > INT32_MAX) return BS_ERR_ARG;
+  if (!pi) return BS_ERR_NULL;
+  for (int i = 0; i < n_parts; ++i)
+    if (!parts[i].indptr || (!parts[i].indices && parts[i].nnz > 0) || (!parts[i].sketches && parts[i].n_rows > 0))
+      return BS_ERR_NULL;
   bs_status st = check_device();
   if (st != BS_OK) return st;
-  if (n_rows == 0) return BS_OK;
+  int64_t rows_total = 0;
+  for (int i = 0; i < n_parts; ++i) rows_total += parts[i].n_rows;
+  if (rows_total == 0) return BS_OK;
+
+  auto part_args = [&](const bs_sketch_part& pt, int32_t G) {
+    SketchArgs a;
+    a.indptr = pt.indptr;
+    a.indices = pt.indices;
+    a.pi = pi;
+    a.pi16 = nullptr;
+    a.out32 = reinterpret_cast<uint32_t*>(pt.sketches);
+    a.pop = pt.popcounts;
+    a.err = err_flag;
+    a.n_rows = pt.n_rows;
+    a.nnz = pt.nnz;
+    a.d = d;
+    a.N = N;
+    a.W32 = N / 32;
+    a.G = G;
+    a.stride = G * a.W32 + G;
+    return a;
+  };
 
   // Map-in-LDS path when the bit-packed map leaves room for staging.
   int lds_max = 0, n_cu = 0;
@@ -775,30 +848,23 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
                        (reinterpret_cast<uintptr_t>(workspace) & 15) == 0;
   if (have_ws && n_cu > 0 && Gl >= 1 && table_words < (INT64_C(1) << 26)) {
     SketchLdsArgs L;
-    L.s.indptr = indptr;
-    L.s.indices = indices;
-    L.s.pi = pi;
-    L.s.pi16 = nullptr;
-    L.s.out32 = reinterpret_cast<uint32_t*>(sketches);
-    L.s.pop = popcounts;
-    L.s.err = err_flag;
-    L.s.n_rows = n_rows;
-    L.s.nnz = nnz;
-    L.s.d = d;
-    L.s.N = N;
-    L.s.W32 = (int32_t)W32;
-    L.s.G = (int32_t)Gl;
-    L.s.stride = (int32_t)(Gl * W32 + Gl);
+    memset(&L, 0, sizeof(L));
+    L.n_parts = n_parts;
+    L.n_windows = 0;
+    for (int i = 0; i < n_parts; ++i) {
+      L.s[i] = part_args(parts[i], (int32_t)Gl);
+      L.n_windows += (parts[i].n_rows + Gl - 1) / Gl;
+    }
     L.bits = bits;
     L.packed = static_cast<const uint32_t*>(workspace);
     L.table_words = (int32_t)table_words;
-    L.n_windows = (n_rows + Gl - 1) / Gl;
-    const size_t lds = (size_t)table_bytes + (size_t)kBigBlockWaves * L.s.stride * 4;
+    const size_t lds = (size_t)table_bytes + (size_t)kBigBlockWaves * L.s[0].stride * 4;
     // one block per CU; fewer when there is less than one window per wave
     int64_t grid = (L.n_windows + kBigBlockWaves - 1) / kBigBlockWaves;
     if (grid > n_cu) grid = n_cu;
     if (grid < 1) grid = 1;
     if ((size_t)lds <= (size_t)lds_max) {
+      split_waves(parts, n_parts, grid * kBigBlockWaves, L.wave_off);
       if (lds > 65536) (void)hipFuncSetAttribute((const void*)sketch_csr_lds_kernel,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       {
@@ -814,28 +880,38 @@ extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, in
     }
   }
 
-  SketchArgs a;
-  a.indptr = indptr;
-  a.indices = indices;
-  a.pi = pi;
-  a.pi16 = nullptr;
-  a.out32 = reinterpret_cast<uint32_t*>(sketches);
-  a.pop = popcounts;
-  a.err = err_flag;
-  a.n_rows = n_rows;
-  a.nnz = nnz;
-  a.d = d;
-  a.N = N;
-  a.W32 = N / 32;
-  int G = kStageWords / a.W32;
-  a.G = G < 1 ? 1 : (G > kMaxRowsPerWave ? kMaxRowsPerWave : G);
-  a.stride = a.G * a.W32 + a.G;
-  const int64_t waves = (n_rows + a.G - 1) / a.G;
-  const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > INT32_MAX) return BS_ERR_ARG;
-  const size_t lds_bytes = (size_t)kWavesPerBlock * a.stride * sizeof(uint32_t);
-  ScopedTiming timing("sketch_csr", as_stream(stream));
-  hipLaunchKernelGGL(sketch_csr_kernel, dim3((unsigned)blocks), dim3(kWavesPerBlock * kWave),
-                     lds_bytes, as_stream(stream), a);
-  return launch_status();
+  // map gathered through L2: one launch per part
+  int G = kStageWords / (N / 32);
+  G = G < 1 ? 1 : (G > kMaxRowsPerWave ? kMaxRowsPerWave : G);
+  for (int i = 0; i < n_parts; ++i) {
+    if (parts[i].n_rows == 0) continue;
+    const SketchArgs a = part_args(parts[i], G);
+    const int64_t waves = (a.n_rows + a.G - 1) / a.G;
+    const int64_t blocks = (waves + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > INT32_MAX) return BS_ERR_ARG;
+    const size_t lds_bytes = (size_t)kWavesPerBlock * a.stride * sizeof(uint32_t);
+    ScopedTiming timing("sketch_csr", as_stream(stream));
+    hipLaunchKernelGGL(sketch_csr_kernel, dim3((unsigned)blocks), dim3(kWavesPerBlock * kWave), lds_bytes,
+                       as_stream(stream), a);
+    st = launch_status();
+    if (st != BS_OK) return st;
+  }
+  return BS_OK;
+}
+
+}  // namespace
+}  // namespace bs
+
+extern "C" bs_status bs_sketch(const int32_t* indptr, const int32_t* indices, int64_t n_rows,
+                               int64_t nnz, const int32_t* pi, int64_t d, int32_t N,
+                               uint64_t* sketches, int32_t* popcounts, int32_t* err_flag,
+                               void* workspace, size_t workspace_bytes, void* stream) {
+  const bs_sketch_part part = {indptr, indices, n_rows, nnz, sketches, popcounts};
+  return bs::sketch_parts_impl(&part, 1, pi, d, N, err_flag, workspace, workspace_bytes, stream);
+}
+
+extern "C" bs_status bs_sketch_parts(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi, int64_t d,
+                                     int32_t N, int32_t* err_flag, void* workspace, size_t workspace_bytes,
+                                     void* stream) {
+  return bs::sketch_parts_impl(parts, n_parts, pi, d, N, err_flag, workspace, workspace_bytes, stream);
 }

@@ -147,3 +147,24 @@ def test_topk_sample_size(lib):
     assert f(2049) == 2048 and f(100_000) == 2048
     assert f(600_000) == 600_000 // 256
     assert f(15360 * 256) == 15360 and f(10**9) == 15360
+
+
+def test_sketch_parts_rejects_bad_arguments(lib):
+    from paper_1910_04658_amd.binding import SketchPart
+    s = lib.bs_sketch_parts
+    good = SketchPart(FAKE, FAKE, 1, 1, FAKE, None)
+    arr = (SketchPart * 5)(good, good, good, good, good)
+    assert s(arr, 0, FAKE, 10, 64, None, None, 0, None) == 2  # no parts
+    assert s(arr, 5, FAKE, 10, 64, None, None, 0, None) == 2  # more than BS_SKETCH_MAX_PARTS
+    assert s(arr, 2, FAKE, 10, 100, None, None, 0, None) == 2  # bad width
+    assert s(arr, 2, FAKE, 0, 64, None, None, 0, None) == 2    # bad d
+    assert s(None, 2, FAKE, 10, 64, None, None, 0, None) == 1  # no parts array
+    assert s(arr, 2, None, 10, 64, None, None, 0, None) == 1   # no map
+    bad = (SketchPart * 2)(good, SketchPart(FAKE, FAKE, -1, 1, FAKE, None))
+    assert s(bad, 2, FAKE, 10, 64, None, None, 0, None) == 2
+    bad = (SketchPart * 2)(good, SketchPart(FAKE, FAKE, 1, 2 ** 31, FAKE, None))
+    assert s(bad, 2, FAKE, 10, 64, None, None, 0, None) == 2
+    bad = (SketchPart * 2)(good, SketchPart(FAKE, None, 1, 5, FAKE, None))
+    assert s(bad, 2, FAKE, 10, 64, None, None, 0, None) == 1
+    bad = (SketchPart * 2)(SketchPart(FAKE, FAKE, 3, 1, None, None), good)
+    assert s(bad, 2, FAKE, 10, 64, None, None, 0, None) == 1

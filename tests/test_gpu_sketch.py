@@ -128,3 +128,49 @@ def _big_corpus():
     from conftest import shared_input
     return shared_input("corpus100k", lambda: datagen.lognormal_corpus(100_000))
 
+
+
+@pytest.mark.parametrize("N", [256, 1024, 4096])
+def test_parts_equal_single_calls(N, dev):
+    """bs_sketch_parts over a corpus, its queries, an empty matrix and a
+    one-row matrix (one map, one launch) writes for every part exactly what
+    bs_sketch writes for it alone, with the map in LDS and gathered from
+    global memory; one part is also checked against the oracle."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    corpus = datagen.lognormal_corpus(30000, d=40000, seed=31)
+    queries = datagen.lognormal_corpus(700, d=40000, seed=32)
+    tiny = datagen.lognormal_corpus(1, d=40000, seed=33)
+    empty_ptr = torch.zeros(1, dtype=torch.int32, device=dev)
+    empty_idx = torch.zeros(0, dtype=torch.int32, device=dev)
+    pi_np = datagen.random_map(40000, N, 34)
+    pi = to_dev(pi_np, dev)
+    mats = [corpus, queries, None, tiny]
+    parts = [(empty_ptr, empty_idx) if m is None else (to_dev(m.indptr, dev), to_dev(m.indices, dev)) for m in mats]
+    for ws in (True, False):
+        flag = torch.zeros(1, dtype=torch.int32, device=dev)
+        res = bs.sketch_parts(parts, pi, N, err_flag=flag, workspace=ws)
+        torch.cuda.synchronize()
+        assert int(flag.item()) == 0
+        for (ip, ix), (w, p) in zip(parts, res):
+            w1, p1 = bs.sketch(ip, ix, pi, N, workspace=ws)
+            torch.cuda.synchronize()
+            assert torch.equal(w, w1) and torch.equal(p, p1)
+    ow, op = oracle.sketch(queries.indptr, queries.indices, queries.d, pi_np, N)
+    assert np.array_equal(words_np(res[1][0]), ow) and np.array_equal(res[1][1].cpu().numpy(), op)
+
+
+def test_parts_error_flag(dev):
+    """An index outside [0, d) in one part raises the call's flag."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    a = datagen.lognormal_corpus(2000, d=5000, seed=35)
+    b = datagen.lognormal_corpus(300, d=5000, seed=36)
+    ix = b.indices.copy()
+    ix[7] = 5000 + 3
+    pi = to_dev(datagen.random_map(5000, 1024, 37), dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    bs.sketch_parts([(to_dev(a.indptr, dev), to_dev(a.indices, dev)), (to_dev(b.indptr, dev), to_dev(ix, dev))],
+                    pi, 1024, err_flag=flag)
+    torch.cuda.synchronize()
+    assert int(flag.item()) & bs.FLAG_INDEX
