@@ -52,6 +52,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kSampleMin = 2048;     // rows scored in the sample pass
 constexpr int kSampleMax = 15360;  // keys fit 60 KB of LDS in the sample select
+constexpr int kSampleBlocks = 1024;  // blocks of the sample-score grid, about
 constexpr int kSelectLdsKeys = 6144; // candidate keys selected in LDS (else in a global buffer)
 constexpr int kMaxSlabs = 2048;      // slot slabs per query at most (the select reads every count at once)
 constexpr int kScanWaves = 16384;    // waves of the scan grid, about
@@ -176,7 +177,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // sample-score grid: 256-row blocks (64 for the word-split pass) x query
   // blocks, ~2k blocks in all
   p.s_rblocks = p.split ? (p.S + kWave - 1) / kWave : (p.S + kThreads - 1) / kThreads;
-  p.s_nqb = (2048 + p.s_rblocks - 1) / p.s_rblocks;
+  p.s_nqb = (kSampleBlocks + p.s_rblocks - 1) / p.s_rblocks;
   if (p.s_nqb > nQ) p.s_nqb = nQ;
   if (p.s_nqb < 1) p.s_nqb = 1;
   p.s_qb = (nQ + p.s_nqb - 1) / p.s_nqb;
@@ -585,9 +586,10 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
     const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc]);
     if (i_ok) a.skeys[(size_t)q * a.S + i] = score_key<M>(sc);
   };
-  if (W32T) {
+  if (W32T && W32T <= 32) {
     // query words on the scalar unit, fetched one query ahead into two
-    // register sets used in turn (no fetched word is moved)
+    // register sets used in turn (no fetched word is moved; two sets of up
+    // to 32 words fit the scalar register file)
     uint32_t qw[2][R];
     int32_t xq[2];
     auto fetch = [&](int b, int64_t q) {
@@ -612,6 +614,36 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
         __builtin_amdgcn_sched_barrier(0);
         emit(q + 1, count(1), xq[1]);
       }
+    }
+  } else if (W32T) {
+    // wider rows: the query streams in pieces of 32 words, each fetched one
+    // piece ahead into two register sets used in turn (an even number of
+    // pieces per row, so every query starts in set 0)
+    constexpr int PS = 32, P = (W32T > 32 ? W32T : 32) / PS;
+    uint32_t buf[2][PS];
+    if (q_begin < q_end) {
+      const cptr<uint32_t> r0 = as_const(Q32 + (size_t)q_begin * W32T);
+#pragma unroll
+      for (int w = 0; w < PS; ++w) buf[0][w] = r0[w];
+    }
+    for (int64_t q = q_begin; q < q_end; ++q) {
+      const int64_t qn = q + 1 < q_end ? q + 1 : q;
+      uint32_t acc = 0;
+      int32_t xq = 0;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        uint32_t(&use)[PS] = buf[p & 1];
+        uint32_t(&fill)[PS] = buf[(p + 1) & 1];
+        const cptr<uint32_t> nr =
+            as_const(Q32 + (p + 1 < P ? (size_t)q * W32T + (p + 1) * PS : (size_t)qn * W32T));
+#pragma unroll
+        for (int w = 0; w < PS; ++w) fill[w] = nr[w];
+        if (p == 0) xq = popQ[q];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int w = 0; w < PS; ++w) acc = bcnt_add(use[w] & cw[p * PS + w], acc);
+      }
+      emit(q, acc, xq);
     }
   } else {
     for (int64_t q = q_begin; q < q_end; ++q) {
