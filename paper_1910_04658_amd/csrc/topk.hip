@@ -383,26 +383,32 @@ __device__ void block_key_range(const K* keys, int64_t n, uint64_t* lo_out, uint
 
 // Descending bitonic sort of n (power of two, <= 2 * kThreads * 8) keys in LDS.
 __device__ void bitonic_sort_desc(uint64_t* v, int n) {
-  if (n <= 2 * kWave) {  // every pair belongs to wave 0: its own LDS order suffices, no block barriers
+  if (n <= 2 * kWave) {
+    // wave 0 sorts in registers: element i in lane i % 64, register i / 64
+    // (missing elements are 0, below every key); partners across lanes are
+    // exchanged with cross-lane swaps, no LDS traffic and no barriers
     if (threadIdx.x < kWave) {
-      const int t = threadIdx.x;
-      for (int size = 2; size <= n; size <<= 1) {
+      const int l = threadIdx.x;
+      uint64_t a = l < n ? v[l] : 0, b = l + kWave < n ? v[l + kWave] : 0;
+#pragma unroll
+      for (int size = 2; size <= 2 * kWave; size <<= 1) {
+#pragma unroll
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          if (t < n / 2) {
-            const int lo = 2 * t - (t & (stride - 1));
-            const int hi = lo + stride;
-            const bool desc = ((lo & size) == 0);
-            const uint64_t a = v[lo], b = v[hi];
-            if (desc ? (a < b) : (a > b)) {
-              v[lo] = b;
-              v[hi] = a;
-            }
+          if (stride == kWave) {  // partners in one lane; size 128 sorts descending
+            const uint64_t hi = a > b ? a : b, lo = a > b ? b : a;
+            a = hi;
+            b = lo;
+          } else {
+            const uint64_t pa = __shfl_xor(a, stride), pb = __shfl_xor(b, stride);
+            const bool lower = (l & stride) == 0;  // this element has the smaller index of its pair
+            const bool da = (l & size) == 0, db = ((l + kWave) & size) == 0;  // descending runs
+            a = (lower == da) ? (a > pa ? a : pa) : (a < pa ? a : pa);
+            b = (lower == db) ? (b > pb ? b : pb) : (b < pb ? b : pb);
           }
-          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
       }
+      if (l < n) v[l] = a;
+      if (l + kWave < n) v[l + kWave] = b;
     }
     __syncthreads();
     return;
@@ -1248,37 +1254,48 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   __shared__ int64_t bneed;
   __shared__ uint32_t nsel;
   __shared__ uint32_t total_s;
+  __shared__ uint32_t above_s;
   constexpr int PER = kMaxSlabs / kThreads;  // slabs per thread
   constexpr int CB = 4;                       // slot planes loaded as one batch
   const int t = threadIdx.x;
-  if (a.qovf[q]) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
-    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
-    return;
+  uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then the slot planes
+  const uint64_t* slots = region + a.S;
+  // 1. one round of loads: the overflow flag, the slab counts, slot plane 0
+  // (most survivors; read whole, it is one dense run), the T table. Thread t
+  // owns slabs t, t + 256, ..., so every count and plane load is one
+  // coalesced run per wave.
+  const int32_t qovf = a.qovf[q];
+  const int64_t ns = a.cnts[q];
+  const int32_t xq = a.popQ[q];
+  const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
+  uint32_t cnt[PER], part = 0;
+  uint64_t v0[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t i = (int64_t)u * kThreads + t;
+    cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
+    v0[u] = i < a.n_slabs ? slots[i] : 0;
   }
   float* lut_s = reinterpret_cast<float*>(sm + a.kpad + a.lds_keys);
   if (LUT)  // read after the barriers of the count below
     for (int x = t; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
   const float* lut = LUT ? lut_s : a.t32;
-  // 1. slab counts: thread t owns slabs t, t + 256, ..., so every load of
-  // counts and of slot planes is one coalesced run per wave
-  const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
-  uint32_t cnt[PER], part = 0;
+  if (t == 0) above_s = 0;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int64_t i = (int64_t)u * kThreads + t;
-    cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
-    part += cnt[u];
-  }
+  for (int u = 0; u < PER; ++u) part += cnt[u];
   const uint32_t incl = block_incl_scan(part, wsum);
   if (t == kThreads - 1) total_s = incl;
   __syncthreads();
-  const int64_t ns = a.cnts[q];
+  if (qovf) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
+    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    return;
+  }
   const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then the slot planes
-  const uint64_t* slots = region + a.S;
-  const int32_t xq = a.popQ[q];
   const float Tq = a.t32[xq];
+  // keys at or above tau (the check below), counted as they are written
+  const uint64_t thr = a.kt < a.k ? (uint64_t)a.qc[q].tau_key << 32 : 0;
+  uint32_t above = 0;
   auto key_of = [&](uint64_t e) { return RAW ? cand_key<M>(e, xq, Tq, lut, a) : e; };
   auto slot = [&](uint32_t c, int u) { return slots[(size_t)c * a.n_slabs + (size_t)u * kThreads + t]; };
   uint64_t* keys;
@@ -1287,20 +1304,31 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
     // the count's scan; planes 0..CB-1 are loaded as one batch, deeper slots
     // (rare) after
     keys = sm + a.kpad;
-    for (int64_t i = t; i < ns; i += kThreads) keys[i] = region[i];
+    for (int64_t i = t; i < ns; i += kThreads) {
+      const uint64_t key = region[i];
+      keys[i] = key;
+      above += key >= thr ? 1u : 0u;
+    }
     uint64_t v[CB][PER];
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
+    for (int u = 0; u < PER; ++u) v[0][u] = v0[u];
+#pragma unroll
+    for (int c = 1; c < CB; ++c)
 #pragma unroll
       for (int u = 0; u < PER; ++u) v[c][u] = cnt[u] > (uint32_t)c ? slot(c, u) : 0;
     uint32_t o = (uint32_t)ns + incl - part;
+    auto put = [&](uint32_t at, uint64_t e) {
+      const uint64_t key = key_of(e);
+      keys[at] = key;
+      above += key >= thr ? 1u : 0u;
+    };
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
 #pragma unroll
       for (int c = 0; c < CB; ++c)
-        if (cnt[u] > (uint32_t)c) keys[o + c] = key_of(v[c][u]);
+        if (cnt[u] > (uint32_t)c) put(o + c, v[c][u]);
 #pragma unroll 4
-      for (uint32_t c = CB; c < cnt[u]; ++c) keys[o + c] = key_of(slot(c, u));
+      for (uint32_t c = CB; c < cnt[u]; ++c) put(o + c, slot(c, u));
       o += cnt[u];
     }
   } else {
@@ -1327,24 +1355,23 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
       uint32_t o = E + pincl - m;
 #pragma unroll
       for (int u = 0; u < PER; ++u)
-        if (cnt[u] > c) keys[o++] = key_of(v[u]);
+        if (cnt[u] > c) {
+          const uint64_t key = key_of(v[u]);
+          keys[o++] = key;
+          above += key >= thr ? 1u : 0u;
+        }
       E += total_s;
     }
+    for (int64_t i = t; i < ns; i += kThreads) above += region[i] >= thr ? 1u : 0u;  // the sample keys stay in place
   }
+  if (above) atomicAdd(&above_s, above);
   __syncthreads();
-  if (a.kt < a.k) {
-    // tau check: with at least k candidates scoring >= tau the true k-th
-    // best score is >= tau, and every row scoring >= tau is a candidate
-    const uint64_t thr = (uint64_t)a.qc[q].tau_key << 32;
-    uint32_t m = 0;
-    for (int64_t i = t; i < n; i += kThreads) m += keys[i] >= thr ? 1u : 0u;
-    const uint32_t above = block_incl_scan(m, wsum);
-    if (t == kThreads - 1) total_s = above;
-    __syncthreads();
-    if (total_s < (uint32_t)a.k) {  // block-uniform: the whole-corpus fallback ranks the query
-      if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
-      return;
-    }
+  // tau check: with at least k candidates scoring >= tau the true k-th best
+  // score is >= tau, and every row scoring >= tau is a candidate (with
+  // kt = k, tau is a lower bound by construction and thr = 0 counts all)
+  if (above_s < (uint32_t)a.k) {  // block-uniform: the whole-corpus fallback ranks the query
+    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    return;
   }
   select_and_write<M>(keys, n, q, a, sel, hist, &bprefix, &bneed, &nsel);
 }
