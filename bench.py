@@ -253,6 +253,56 @@ def jaccard_mse(step, corpus, queries):
             "top100_pairs": mse_top, "top100_mean_estimate": mean_js_top}
 
 
+def ranking_eval(dev, max_queries=500, widths=(256, 1024, 4096)):
+    """Threshold retrieval (Section 5, Experiment 2) on synthetic rows with
+    planted near-duplicates, split 90/10 into corpus and queries: for every
+    query the corpus rows whose similarity reaches each of the paper's
+    thresholds, from bs_estimate on the sketches against the exact
+    similarities (sparse products on the host); accuracy, precision, recall
+    and F1 pooled over (query, row) pairs, per sketch width."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    import datagen
+    from paper_1910_04658_amd import binding as bs
+    from paper_1910_04658_amd import ranking
+    corpus, queries = datagen.ranking_split()
+    queries = queries.take(np.arange(min(max_queries, queries.n)))
+
+    def mat(c):
+        return sp.csr_matrix((np.ones(c.nnz, np.float64), c.indices, c.indptr), shape=(c.n, c.d))
+
+    Qm, Cm = mat(queries), mat(corpus)
+    inter = (Qm @ Cm.T).toarray()
+    la = np.asarray(Qm.sum(1)).ravel()[:, None]
+    lb = np.asarray(Cm.sum(1)).ravel()[None, :]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        exact = {"ip": inter,
+                 "js": np.where(la + lb - inter > 0, inter / (la + lb - inter), 0.0),
+                 "cos": np.where(la * lb > 0, inter / np.sqrt(la * lb), 0.0)}
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    parts = [(to(corpus.indptr), to(corpus.indices)), (to(queries.indptr), to(queries.indices))]
+    out = {"corpus_rows": corpus.n, "queries": queries.n, "pairs": int(inter.size), "thresholds": list(ranking.THRESHOLDS),
+           "ip_thresholds": "fractions of the largest exact inner product", "widths": {}}
+    for N in widths:
+        pi = to(datagen.random_map(corpus.d, N, datagen.SEED_PI + 11 + N))
+        (C, pC), (Q, pQ) = bs.sketch_parts(parts, pi, N)
+        est = bs.estimate(Q, C, N, measures=("ip", "js", "cos"), popA=pQ, popB=pC)
+        torch.cuda.synchronize()
+        res = {}
+        for m in ("js", "cos", "ip"):
+            e = est[m].cpu().numpy()
+            th = ranking.ip_thresholds(exact["ip"]) if m == "ip" else ranking.THRESHOLDS
+            met = ranking.threshold_metrics(e, exact[m], th)
+            res[m] = [[round(t, 4), round(v["accuracy"], 4), round(v["precision"], 4), round(v["recall"], 4),
+                       round(v["f1"], 4), v["truth"], v["found"]] for t, v in met.items()]
+        out["widths"][str(N)] = res
+        del est
+    out["columns"] = ["threshold", "accuracy", "precision", "recall", "f1", "truth_pairs", "found_pairs"]
+    return out
+
+
 def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256, steps=600, batch=65536):
     """Learned estimator vs closed form: train on ~10M near-duplicate pairs of
     the benchmark distribution sketched at N = 256, test on ~1M held-out pairs."""
@@ -435,6 +485,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mse", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-estimator evaluation")
+    ap.add_argument("--no-ranking", action="store_true", help="skip the threshold-retrieval evaluation")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
     ap.add_argument("--graph", action="store_true", help="time replays of the step recorded into a HIP graph")
@@ -560,6 +611,10 @@ def main():
         log("training the learned estimator ...")
         out["learned_estimator"] = learned_eval(dev)
         log("learned estimator: %s" % out["learned_estimator"])
+    if not args.no_ranking:
+        log("threshold retrieval (ranking experiment) ...")
+        out["ranking"] = ranking_eval(dev)
+        log("ranking: %s" % json.dumps(out["ranking"]["widths"].get(str(args.N))))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample ...")
         out["cpu_baseline"] = cpu_baseline(corpus, queries, pis[args.N], args.N, k, args.cpu_queries)

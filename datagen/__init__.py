@@ -416,6 +416,36 @@ def device_corpus_chunks(n: int, d: int, mean: float, sd: float, seed: int, devi
         yield indptr.to(torch.int32), perm[ranks].to(torch.int32)
 
 
+SEED_RANKING = 5005
+
+
+def concat_rows(a: CSR, b: CSR) -> CSR:
+    """The rows of a, then the rows of b (same dimension)."""
+    if a.d != b.d:
+        raise ValueError("dimensions differ")
+    indptr = np.concatenate([a.indptr[:-1].astype(np.int64), b.indptr.astype(np.int64) + a.nnz])
+    if indptr[-1] >= 2 ** 31:
+        raise ValueError("nnz does not fit int32 indptr; split the batch")
+    return CSR(indptr.astype(np.int32), np.concatenate([a.indices, b.indices]).astype(np.int32), a.d)
+
+
+def ranking_split(n_background: int = 20_000, n_groups: int = 1000, group_size: int = 10, d: int = 100_000,
+                  seed: int = SEED_RANKING, query_frac: float = 0.1):
+    """Data of the ranking experiment (Section 5, Experiment 2) on synthetic
+    rows: `n_background` rows of the benchmark distribution plus `n_groups`
+    groups of `group_size` near-duplicates (variant_groups), so that exact
+    similarities reach the high thresholds, shuffled and split into a
+    corpus (1 - query_frac of the rows) and queries, the queries in random
+    order (so any prefix is a random sample). Returns (corpus, queries)."""
+    rng = np.random.default_rng(seed)
+    bg = lognormal_corpus(n_background, d=d, seed=int(rng.integers(1 << 62)))
+    gr = variant_groups(n_groups, group_size, d=d, seed=int(rng.integers(1 << 62))).csr
+    rows = concat_rows(bg, gr)
+    perm = rng.permutation(rows.n)
+    nq = int(round(query_frac * rows.n))
+    return rows.take(np.sort(perm[nq:])), rows.take(perm[:nq])
+
+
 def loguniform_lengths(rng: np.random.Generator, n: int, lo: int, hi: int) -> np.ndarray:
     """Integer lengths with log-uniform distribution on [lo, hi]."""
     return np.exp(rng.uniform(math.log(lo), math.log(hi + 1), n)).astype(np.int64).clip(lo, hi)

@@ -1,0 +1,51 @@
+"""Threshold retrieval (Section 5, Experiment 2) from GPU estimates against
+the oracle: the pairs found at each threshold from bs_estimate equal those
+found from the oracle's FP64 estimates (a pair may differ only where the
+oracle's estimate is within the FP64 tolerance of the threshold), and the
+library's metrics equal the oracle's plain-set metrics."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from helpers import to_dev
+from oracle import ranking as oref
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("N", [256, 1024])
+def test_threshold_retrieval_matches_oracle(N, dev):
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    from paper_1910_04658_amd import ranking
+    corpus, queries = datagen.ranking_split(800, 40, 8, d=20000, seed=77)
+    pi = datagen.random_map(corpus.d, N, 78)
+    parts = [(to_dev(corpus.indptr, dev), to_dev(corpus.indices, dev)),
+             (to_dev(queries.indptr, dev), to_dev(queries.indices, dev))]
+    (C, pC), (Q, pQ) = bs.sketch_parts(parts, to_dev(pi, dev), N)
+    est = bs.estimate(Q, C, N, measures=("ip", "js", "cos"), popA=pQ, popB=pC)
+    torch.cuda.synchronize()
+    # oracle: sketch sets, pair counts, FP64 estimates; exact sets, exact measures
+    SQ = oracle.sketch_sets(queries.indptr, queries.indices, queries.d, pi, N)
+    SC = oracle.sketch_sets(corpus.indptr, corpus.indices, corpus.d, pi, N)
+    o_est = oracle.estimate_pairs(SQ.length, SC.length, oracle.intersections(SQ, SC), N)
+    EQ = oracle.normalize(queries.indptr, queries.indices, queries.d)
+    EC = oracle.normalize(corpus.indptr, corpus.indices, corpus.d)
+    inter = oracle.intersections(EQ, EC).astype(np.float64)
+    la, lb = EQ.length[:, None].astype(np.float64), EC.length[None, :].astype(np.float64)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        exact = {"ip": inter, "js": np.where(la + lb - inter > 0, inter / (la + lb - inter), 0.0),
+                 "cos": np.where(la * lb > 0, inter / np.sqrt(la * lb), 0.0)}
+    for m, row in (("ip", oracle.IP), ("js", oracle.JS), ("cos", oracle.COS)):
+        g = est[m].cpu().numpy()
+        o = o_est[row]
+        th = ranking.ip_thresholds(exact["ip"]) if m == "ip" else ranking.THRESHOLDS
+        lib = ranking.threshold_metrics(g, exact[m], th)
+        assert any(v["truth"] > 0 for v in lib.values()), "no true pairs at any threshold"
+        for t in th:
+            diff = (g >= t) != (o >= t)
+            assert np.all(np.abs(o[diff] - t) <= 1e-6 * max(abs(t), 1.0)), (m, t)
+            ref = oref.set_metrics(oref.retrieved(exact[m].tolist(), t), oref.retrieved(o.tolist(), t))
+            if not diff.any():
+                assert lib[float(t)] == pytest.approx(ref), (m, t)
