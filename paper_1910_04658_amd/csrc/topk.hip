@@ -899,15 +899,21 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
     for (int w = 0; w < PS; ++w) buf[0][w] = r0[w];
   }
-  auto mrow = [&](int32_t x) {  // row x of the threshold table (uniform)
-    return reinterpret_cast<const char*>(mt + (size_t)(uint32_t)x * (uint32_t)a.nQp);
+  // row x of the threshold table as a buffer resource (scalar registers), so
+  // a lane's threshold load takes its column offset and no address arithmetic
+  auto mrow = [&](int32_t x) {
+    const uint16_t* r = mt + (size_t)(uint32_t)x * (uint32_t)a.nQp;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)r, (short)0, (int)(a.nQp * 2), 0x00020000);
+  };
+  auto mload = [&](__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
   };
   int32_t xcur = popC[cb];  // weight of the current row
   uint16_t m[QPL];
   {
-    const char* mr = mrow(xcur);
+    const auto mr = mrow(xcur);
 #pragma unroll
-    for (int j = 0; j < QPL; ++j) m[j] = *reinterpret_cast<const uint16_t*>(mr + moff[j]);
+    for (int j = 0; j < QPL; ++j) m[j] = mload(mr, moff[j]);
   }
   int32_t x2 = popC[cb + 1 < ce ? cb + 1 : cb];  // weight of the next row
 
@@ -932,9 +938,9 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
       for (int w = 0; w < PS; ++w) fill[w] = nr[w];
       if (p == 0) {
         x3 = popC[c2];
-        const char* mr = mrow(x2);
+        const auto mr = mrow(x2);
 #pragma unroll
-        for (int j = 0; j < QPL; ++j) mn[j] = *reinterpret_cast<const uint16_t*>(mr + moff[j]);
+        for (int j = 0; j < QPL; ++j) mn[j] = mload(mr, moff[j]);
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -952,7 +958,10 @@ __device__ __forceinline__ void scan_body(const TopkArgs& a, int64_t bid) {
     for (int j = 0; j < QPL; ++j) {
       const bool take = q_ok[j] && !in_sample && acc[j] >= (uint32_t)m[j];
       if (take) {
-        if (cnt[j] < a.scap) dst[j][(size_t)cnt[j] * a.n_slabs] = raw_entry(acc[j], xcur, c, a.N);
+        if ((uint32_t)cnt[j] < (uint32_t)a.scap) {  // dst[j] walks the query's slot planes
+          *dst[j] = raw_entry(acc[j], xcur, c, a.N);
+          dst[j] += a.n_slabs;
+        }
         ++cnt[j];
       }
       m[j] = mn[j];
