@@ -1070,7 +1070,30 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
   const uint16_t* mt = a.mtab + q;  // q < nQp
   int64_t next_s = (c_begin + a.stride - 1) / a.stride * a.stride;  // next sampled row at or after the rows seen
   const int64_t s_end = a.S * a.stride;
+  // The rows this wave finishes in a block of kSplitRows: with 64-word
+  // quarters their weights are fetched one block ahead and their thresholds
+  // at the start of the block, so both arrive while the block's counts are
+  // formed (with 128-word quarters that measured slower: they are loaded
+  // when the rows are finished).
+  constexpr int FR = kSplitRows / kSplitWaves;
+  constexpr bool PIPE = WS <= 64;
+  int32_t xw[FR];
+  auto fetch_weights = [&](int64_t b0, int32_t (&x)[FR]) {
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      const int64_t c = b0 + wid + i * kSplitWaves;
+      x[i] = popC[c < c_end ? c : c_end - 1];
+    }
+  };
+  if (PIPE) fetch_weights(c_begin, xw);
   for (int64_t c0 = c_begin; c0 < c_end; c0 += kSplitRows) {
+    uint16_t mw[FR];
+    int32_t xn[FR];
+    if (PIPE) {
+#pragma unroll
+      for (int i = 0; i < FR; ++i) mw[i] = mt[(size_t)(uint32_t)xw[i] * (uint32_t)a.nQp];
+      fetch_weights(c0 + kSplitRows < c_end ? c0 + kSplitRows : c0, xn);
+    }
 #pragma unroll 2
     for (int r = 0; r < kSplitRows; ++r) {
       const int64_t c = c0 + r < c_end ? c0 + r : c_end - 1;  // rows past the end are not finished
@@ -1084,7 +1107,9 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
       part[r][wid][lane] = acc;
     }
     __syncthreads();
-    for (int r = wid; r < kSplitRows; r += kSplitWaves) {
+#pragma unroll
+    for (int i = 0; i < FR; ++i) {
+      const int r = wid + i * kSplitWaves;
       const int64_t c = c0 + r;
       if (c >= c_end) break;  // wave-uniform
       uint32_t x = 0;
@@ -1092,12 +1117,19 @@ __device__ __forceinline__ void scan_split_body(const TopkArgs& a, int64_t bid) 
       for (int w = 0; w < kSplitWaves; ++w) x += part[r][w][lane];
       while (next_s < c) next_s += a.stride;
       const bool in_sample = c == next_s && c < s_end;
-      const int32_t xc = popC[c];
-      const uint16_t m = mt[(size_t)xc * a.nQp];
-      if (q_ok && !in_sample && x >= (uint32_t)m) {
-        if (cnt < a.scap) dst[(size_t)cnt * a.n_slabs] = raw_entry(x, xc, c, a.N);
+      const int32_t xc = PIPE ? xw[i] : popC[c];
+      const uint32_t m = PIPE ? (uint32_t)mw[i] : (uint32_t)mt[(size_t)(uint32_t)xc * (uint32_t)a.nQp];
+      if (q_ok && !in_sample && x >= m) {
+        if ((uint32_t)cnt < (uint32_t)a.scap) {  // dst walks the query's slot planes
+          *dst = raw_entry(x, xc, c, a.N);
+          dst += a.n_slabs;
+        }
         ++cnt;
       }
+    }
+    if (PIPE) {
+#pragma unroll
+      for (int i = 0; i < FR; ++i) xw[i] = xn[i];
     }
     __syncthreads();
   }
