@@ -118,6 +118,8 @@ def load():
             L.bs_debug_set_topk_limits.restype = ctypes.c_int
             L.bs_debug_set_topk_tau_rank.argtypes = [i64]
             L.bs_debug_set_topk_tau_rank.restype = ctypes.c_int
+            L.bs_debug_set_topk_mma.argtypes = [i32]
+            L.bs_debug_set_topk_mma.restype = ctypes.c_int
             BI, BSh = ctypes.POINTER(BatchItem), ctypes.POINTER(BatchShape)
             L.bs_batch_workspace_size.argtypes = [BI, i32]
             L.bs_batch_workspace_size.restype = sz
@@ -384,6 +386,12 @@ def debug_set_topk_tau_rank(rank: int = -1):
     """Test hook: take the filter threshold as the rank-th best sample score
     (below the automatic rank; -1 = automatic)."""
     load().bs_debug_set_topk_tau_rank(int(rank))
+
+
+def debug_set_topk_mma(on: bool = True):
+    """Test hook: False forms the scan's pair counts on the vector ALU even
+    where the matrix-core scan applies (True = automatic)."""
+    load().bs_debug_set_topk_mma(1 if on else 0)
 
 
 def timing_enable(on: bool = True):

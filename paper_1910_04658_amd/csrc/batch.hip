@@ -45,6 +45,15 @@ std::vector<TopkTune> candidate_tunes(int32_t N) {
   const int qpls[3] = {1, 2, 4};
   // the word-split scan (256 and 512 words) also tries a finer grid
   const int waves[4] = {4096, 8192, 16384, 32768};
+  if (N % 512 == 0) {  // the matrix-core scan: only the grid size varies
+    for (int w : waves) {
+      TopkTune t;
+      t.qpl = 1;
+      t.waves = w;
+      c.push_back(t);
+    }
+    return c;
+  }
   const int n_waves = W32 >= 256 ? 4 : 3;
   for (int q : qpls) {
     if ((q == 2 && !(pow2 && W32 <= 32)) || (q == 4 && !(pow2 && W32 <= 16))) continue;

@@ -62,6 +62,8 @@ constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the 
 constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, about
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFallbackBlocks = 16;
+constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
+constexpr int kMmaWaves = 16384;     // waves of the matrix-core scan grid, about
 
 struct QConst {  // per-query constants written by the sample pass
   float tau;     // (a lower bound on) the kt-th best sample score
@@ -79,6 +81,7 @@ struct Plan {
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
   bool rows;                                          // row-lane scan (small batches)
   bool split;                                         // word-split scan (wide sketches)
+  bool mma;                                           // matrix-core scan (replaces the two above)
   bool sel_lut;                                       // select keeps T in LDS
   int64_t lds_keys;                                   // select: candidate keys held in LDS
   size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_qovf,
@@ -133,8 +136,21 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // Sketches of 256 or 512 words do not fit one lane's registers: four waves
   // share a 64-query group, each holding a quarter of the words.
   p.split = !p.rows && pow2 && (W32 == 256 || W32 == 512);
-  if (p.rows || p.split) p.qpl = 1;
-  if (p.split) {
+  // Widths of whole 512-bit chunks scan on the matrix cores (the word-split
+  // sample pass is kept for the wide ones).
+  p.mma = !p.rows && tune.mma != 0 && N % 512 == 0;
+  if (p.rows || p.split || p.mma) p.qpl = 1;
+  if (p.mma) {
+    p.ngrp = nqb;
+    p.nqb4 = (nqb + 3) / 4;  // a block: four 64-query groups x one slab
+    const int64_t waves = tune.waves > 0 ? tune.waves : kMmaWaves;
+    const int64_t per = 4 * (p.nqb4 > 0 ? p.nqb4 : 1);  // waves per slab (a batch may hold no queries)
+    int64_t n_slabs = (waves + per - 1) / per;
+    if (n_slabs > kMaxSlabs) n_slabs = kMaxSlabs;
+    if (n_slabs < 1) n_slabs = 1;
+    const int64_t tiles = (nC + kMmaRows - 1) / kMmaRows;
+    p.slab = (tiles + n_slabs - 1) / n_slabs * kMmaRows;  // whole wave tiles
+  } else if (p.split) {
     p.ngrp = nqb;
     p.nqb4 = nqb;  // one block per (row slab, query group)
     const int64_t waves = tune.waves > 0 ? tune.waves : kSplitGridWaves;
@@ -164,8 +180,9 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // deviations and a margin for ties at the threshold, so that overflow into
   // the fallback path is rare
   // (a slot slab of the word-split scan is one wave's quarter of a row slab)
-  const int64_t slot_rows = p.split ? (p.slab + kSplitWaves - 1) / kSplitWaves : p.slab;
-  if (p.split) p.n_slabs *= kSplitWaves;
+  const bool wsplit = p.split && !p.mma;
+  const int64_t slot_rows = wsplit ? (p.slab + kSplitWaves - 1) / kSplitWaves : p.slab;
+  if (wsplit) p.n_slabs *= kSplitWaves;
   const double e = p.S > 0 ? (double)slot_rows * (double)p.kt / (double)p.S : 0.0;
   int64_t scap = (int64_t)ceil(2.0 * e + 6.0 * sqrt(e)) + 8;
   p.scap = scap < slot_rows ? scap : slot_rows;
@@ -456,6 +473,7 @@ struct TopkArgs {
   int32_t N, W32, k, kpad;
   int32_t kt;                      // rank of tau in the sample (<= k)
   int32_t qpl, rows, split;        // scan variant: queries per lane, row-lane scan, word-split scan
+  int32_t mma;                     // matrix-core scan (split then only selects the sample kernel)
   int32_t sel_lut;                 // the select keeps T in LDS
 };
 
@@ -504,6 +522,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.qpl = c->qpl;
   a.rows = c->rows;
   a.split = c->split;
+  a.mma = c->mma;
   a.sel_lut = c->sel_lut;
   return a;
 }
@@ -1144,6 +1163,248 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
   return ((uint64_t)score_key<M>(sc) << 32) | (uint64_t)(~idx);
 }
 
+// Matrix-core scan. The pair counts of 16 queries x 16 corpus rows are one
+// product of 0/1 matrices over the N sketch bits (x_ab = sum over bits of
+// q_bit * c_bit), formed exactly on the matrix cores with FP4 (E2M1)
+// operands. A 512-bit chunk of a row is held by a 16-lane column of the
+// wave as 16 words (lane l: row l % 16, words 4 (l / 16) .. +3), and bit
+// class d (bits 4i + d of every word) becomes an FP4 operand by a mask
+// alone: class 0 keeps nibble bit 0 (the value 0.5), class 1 bit 1 (1.0),
+// class 2 bit 2 (2.0), and class 3 is shifted down three places (0.5). Each
+// class is one v_mfma_scale_f32_16x16x128_f8f6f4 whose block scales make
+// every product of two set bits exactly 1.0, so the FP32 accumulators hold
+// exact counts (N <= 2^24). A and B take the same bit order, so the product
+// is the plain AND-popcount whatever order the unit sums in.
+//
+// A wave owns one 64-query group and the rows of its slab in tiles of 64
+// (4 x 4 MFMA tiles, 64 accumulators per lane); the four waves of a block
+// take four query groups of the same slab. The epilogue reads, per lane and
+// 16-query tile, the four consecutive bounds m[x_c][q..q+3] of its row in
+// one 8-byte load; survivors are numbered by wave ballots, no atomics.
+typedef int bs_v8i __attribute__((ext_vector_type(8)));
+typedef float bs_v4f __attribute__((ext_vector_type(4)));
+
+template <int D>
+__device__ __forceinline__ bs_v8i fp4_class(uint2 lo, uint2 hi) {
+  const uint32_t w[4] = {lo.x, lo.y, hi.x, hi.y};
+  bs_v8i r = {0, 0, 0, 0, 0, 0, 0, 0};  // FP4 operands use the low four words
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    r[j] = (int)(D == 0 ? (w[j] & 0x11111111u)
+                        : D == 1 ? (w[j] & 0x22222222u) : D == 2 ? (w[j] & 0x44444444u) : ((w[j] >> 3) & 0x11111111u));
+  return r;
+}
+
+// E8M0 block scale of class D: 2 for the 0.5 classes, 1, 1/2 for the 2.0 class
+template <int D>
+__device__ __forceinline__ bs_v4f mma_class(bs_v8i a, bs_v8i b, bs_v4f c) {
+  constexpr int sc = D == 1 ? 127 : (D == 2 ? 126 : 128);
+  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, sc, 0, sc);
+}
+
+// KCT: 512-bit chunks per row when fixed at compile time (the chunk loop is
+// then unrolled, which keeps the accumulators in place), 0 for any width.
+template <int KCT>
+__device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
+  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int i = lane % 16, g = lane / 16;
+  const int64_t sl = bid / a.nqb4;
+  const int64_t qg = (bid % a.nqb4) * (kThreads / kWave) + wid;  // 64-query group
+  const int64_t c_begin = sl * a.slab;
+  const int64_t c_end = c_begin + a.slab < a.nC ? c_begin + a.slab : a.nC;
+  if (qg * kWave >= a.nQ || c_begin >= c_end) return;  // wave-uniform
+  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 16;
+  const int32_t ntiles = (int32_t)((c_end - c_begin + kMmaRows - 1) / kMmaRows);
+  // Operands are read as a uniform base (scalar registers) plus a 32-bit lane
+  // offset. A rows: query qg*64 + 16 qb + i (past the batch: the last query,
+  // masked later by its bound); B rows: tile row 16 t + i (past the slab: its
+  // last row, masked in the epilogue).
+  const uint32_t rowb = (uint32_t)W32 * 4u;  // bytes per row
+  const char* qbase = reinterpret_cast<const char*>(a.Q) + (size_t)qg * kWave * rowb;
+  const char* cslab = reinterpret_cast<const char*>(a.C) + (size_t)c_begin * rowb;
+  const uint32_t nrows = (uint32_t)(c_end - c_begin);
+  uint32_t qoff[4];
+#pragma unroll
+  for (int qb = 0; qb < 4; ++qb) {
+    int64_t q = qg * kWave + 16 * qb + i;
+    q = q < a.nQ ? q : a.nQ - 1;
+    qoff[qb] = (uint32_t)(q - qg * kWave) * rowb + 16u * g;
+  }
+  auto load_a = [&](int ch, uint2 (&qa)[4][2]) {
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+      const uint2* p = reinterpret_cast<const uint2*>(qbase + (qoff[qb] + 64u * ch));
+      qa[qb][0] = p[0];
+      qa[qb][1] = p[1];
+    }
+  };
+  auto load_b = [&](int32_t tile, int ch, uint2 (&cb)[4][2]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
+      r = r < nrows ? r : nrows - 1;
+      const uint2* p = reinterpret_cast<const uint2*>(cslab + (r * rowb + 16u * g + 64u * ch));
+      cb[t][0] = p[0];
+      cb[t][1] = p[1];
+    }
+  };
+  auto load_xc = [&](int32_t tile, int32_t (&xc)[4]) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
+      r = r < nrows ? r : nrows - 1;
+      xc[t] = a.popC[c_begin + r];
+    }
+  };
+  // bounds of the lane's four queries of each 16-query tile: m[x][qg*64 + 16 qb + 4 g + 0..3]
+  const uint16_t* mcol = a.mtab + qg * kWave + 4 * g;
+  const uint32_t stride = (uint32_t)a.stride;
+  const int64_t s_end64 = a.S * a.stride < a.nC ? a.S * a.stride : a.nC;
+  const uint32_t s_end = (uint32_t)s_end64;
+  // first sampled row at or after the slab start (rows past s_end are never sampled)
+  uint32_t next_s = (uint32_t)((c_begin + a.stride - 1) / a.stride * a.stride);
+  // Survivors of query (qb, g, rr) = qg*64 + 16 qb + 4 g + rr are numbered by
+  // a ballot over the 16 lanes of group g; cnt[qb][rr] holds the group's
+  // running count (the same in its 16 lanes). Slot s of that query lies at
+  // cbase + (16 qb + rr) * kmax + s * n_slabs.
+  uint64_t* const cbase = a.cands + (size_t)(qg * kWave + 4 * g) * a.kmax + a.S + sl;
+  const int32_t scap = (int32_t)a.scap;
+  const uint32_t nsl = (uint32_t)a.n_slabs;
+  const uint64_t gmask = 0xffffull << (16 * g);
+  int32_t cnt[4][4];
+#pragma unroll
+  for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) cnt[qb][rr] = 0;
+
+  // software pipeline: the operands of the next (tile, chunk) step load while
+  // the current one is multiplied; the row weights of the next tile load
+  // during the current tile's epilogue
+  // with at most two chunks the query words stay in registers for the whole slab
+  constexpr bool HOLD = KCT > 0 && KCT <= 2;
+  uint2 qh[HOLD ? KCT : 1][4][2];
+  if constexpr (HOLD) {
+#pragma unroll
+    for (int ch = 0; ch < KCT; ++ch) load_a(ch, qh[ch]);
+  }
+  uint2 qa[4][2], cb[4][2];
+  if constexpr (!HOLD) load_a(0, qa);
+  load_b(0, 0, cb);
+  int32_t xc[4];
+  load_xc(0, xc);
+  for (int32_t tile = 0; tile < ntiles; ++tile) {
+    if constexpr (HOLD) {  // expand the held words anew per tile (hoisted, they would take 64 registers per chunk)
+#pragma unroll
+      for (int ch = 0; ch < (HOLD ? KCT : 1); ++ch)
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) asm volatile("" : "+v"(qh[ch][qb][0]), "+v"(qh[ch][qb][1]));
+    }
+    bs_v4f acc[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) acc[t][qb] = bs_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    constexpr int KU = KCT > 0 && KCT <= 2 ? KCT : 1;
+#pragma unroll KU
+    for (int ch = 0; ch < KC; ++ch) {
+      // next step (the last step reloads itself: in bounds, unused)
+      const bool last = ch + 1 == KC;
+      const int32_t nt = last ? (tile + 1 < ntiles ? tile + 1 : tile) : tile;
+      const int nch = last ? (tile + 1 < ntiles ? 0 : ch) : ch + 1;
+      uint2 qn[4][2], cn[4][2];
+      if constexpr (!HOLD) load_a(nch, qn);
+      load_b(nt, nch, cn);
+      auto klass = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        bs_v8i A[4];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+          A[qb] = HOLD ? fp4_class<D>(qh[HOLD ? ch : 0][qb][0], qh[HOLD ? ch : 0][qb][1]) : fp4_class<D>(qa[qb][0], qa[qb][1]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const bs_v8i B = fp4_class<D>(cb[t][0], cb[t][1]);
+#pragma unroll
+          for (int qb = 0; qb < 4; ++qb) acc[t][qb] = mma_class<D>(A[qb], B, acc[t][qb]);
+        }
+      };
+      klass(std::integral_constant<int, 0>());
+      klass(std::integral_constant<int, 1>());
+      klass(std::integral_constant<int, 2>());
+      klass(std::integral_constant<int, 3>());
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if constexpr (!HOLD) {
+          qa[u][0] = qn[u][0];
+          qa[u][1] = qn[u][1];
+        }
+        cb[u][0] = cn[u][0];
+        cb[u][1] = cn[u][1];
+      }
+    }
+    // the next tile's row weights load during this tile's epilogue
+    int32_t xcur[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xcur[t] = xc[t];
+    load_xc(tile + 1 < ntiles ? tile + 1 : tile, xc);
+    // sampled rows of this tile (scored in the sample pass): one bit per row
+    const uint32_t r0 = (uint32_t)(c_begin + (int64_t)tile * kMmaRows);
+    const uint32_t r_hi = (uint32_t)(c_begin + (int64_t)tile * kMmaRows + kMmaRows < c_end
+                                         ? c_begin + (int64_t)tile * kMmaRows + kMmaRows
+                                         : c_end);
+    uint64_t smask = 0;
+    while (next_s < r_hi && next_s < s_end) {
+      smask |= 1ull << (next_s - r0);
+      next_s += stride;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const uint32_t r = r0 + 16 * t + i;
+      const bool row_ok = r < r_hi && !((smask >> (16 * t + i)) & 1);
+      const uint16_t* mrow = mcol + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
+      uint2 mt[4];
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) mt[qb] = *reinterpret_cast<const uint2*>(mrow + 16 * qb);
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) {
+        __builtin_amdgcn_sched_barrier(0);  // one 16-query tile at a time: short live ranges
+        const uint2 mm = mt[qb];
+        const uint32_t m4[4] = {mm.x & 0xffffu, mm.x >> 16, mm.y & 0xffffu, mm.y >> 16};
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const uint32_t x = (uint32_t)acc[t][qb][rr];
+          const bool take = row_ok && x >= m4[rr];  // bounds of queries past the batch are 65535 > N
+          const uint64_t bal = __ballot(take);
+          if (bal) {  // wave-uniform
+            const uint64_t gb = bal & gmask;
+            const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(gb >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)gb, 0u));
+            const int32_t slot = cnt[qb][rr] + rank;
+            if (take && slot < scap)
+              cbase[(size_t)(16 * qb + rr) * a.kmax + (uint32_t)slot * nsl] = raw_entry(x, xcur[t], r, a.N);
+            cnt[qb][rr] += __popcll(gb);
+          }
+        }
+      }
+    }
+  }
+  // lane l reports query qg*64 + l = (qb, g', rr) = (l / 16, (l % 16) / 4, l % 4),
+  // whose count sits in every lane of group g'
+  int32_t n = 0;
+  const int src = 16 * ((lane % 16) / 4);
+#pragma unroll
+  for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int32_t v = __shfl(cnt[qb][rr], src);
+      if (qb == lane / 16 && rr == lane % 4) n = v;
+    }
+  const int64_t q = qg * kWave + lane;
+  if (q < a.nQ) {
+    a.scnt[(size_t)q * a.n_slabs + sl] = n < scap ? n : scap;
+    if (n > scap) a.qovf[q] = 1;
+  }
+}
+
 // Row-lane scan for batches of at most 64 queries. Each wave owns one slab:
 // a run of 64-row tiles. Lane l holds row (tile + l) in VGPRs; the queries
 // arrive in turn on the scalar unit, so the corpus is read from HBM exactly
@@ -1524,6 +1785,10 @@ template <bool ONE, int WS>
 __global__ __launch_bounds__(kThreads) void topk_scan_split_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_split_body<WS>(a, lb)))
 }
+template <bool ONE, int KCT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void topk_scan_mma_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((scan_mma_body<KCT>(a, lb)))
+}
 template <bool ONE, int M, int W32T>
 __global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_rows_body<M, W32T>(a, lb)))
@@ -1555,6 +1820,7 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
     case kStScan:
       if (!scan) return 0;
       if (a.rows) return (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave);
+      if (a.mma) return a.n_slabs * a.nqb4;
       if (a.split) return (a.n_slabs / kSplitWaves) * a.nqb4;
       return a.n_slabs * a.nqb4;
     case kStSelect: return a.nQ;
@@ -1611,6 +1877,15 @@ const void* stage_kernel(const TopkArgs& a, int st) {
           case 32: return (const void*)topk_scan_rows_kernel<ONE, M, 32>;
           case 64: return (const void*)topk_scan_rows_kernel<ONE, M, 64>;
           default: return (const void*)topk_scan_rows_kernel<ONE, M, 128>;
+        }
+      }
+      if (a.mma) {
+        switch (W32 / 16) {
+          case 1: return (const void*)topk_scan_mma_kernel<ONE, 1>;
+          case 2: return (const void*)topk_scan_mma_kernel<ONE, 2>;
+          case 4: return (const void*)topk_scan_mma_kernel<ONE, 4>;
+          case 8: return (const void*)topk_scan_mma_kernel<ONE, 8>;
+          default: return (const void*)topk_scan_mma_kernel<ONE, 0>;
         }
       }
       if (a.split) return W32 == 256 ? (const void*)topk_scan_split_kernel<ONE, 64> : (const void*)topk_scan_split_kernel<ONE, 128>;
@@ -1719,6 +1994,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.qpl = (int32_t)p.qpl;
   a.rows = p.rows ? 1 : 0;
   a.split = p.split ? 1 : 0;
+  a.mma = p.mma ? 1 : 0;
   a.sel_lut = p.sel_lut ? 1 : 0;
 }
 
@@ -1728,6 +2004,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
 static int64_t g_scap_override = -1;
 static int64_t g_ldskeys_override = -1;
 static int64_t g_taurank_override = -1;
+static int32_t g_mma_override = -1;
 
 // ---- group plans ----------------------------------------------------------------
 struct TopkGroup {
@@ -1792,7 +2069,7 @@ bs_status topk_group_create(const TopkItem* items, const TopkTune* tunes, int32_
     int32_t c = -1;
     for (size_t j = 0; j < G->classes.size(); ++j) {
       const TopkArgs& r = G->args[G->classes[j][0]];
-      if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.qpl == G->args[i].qpl &&
+      if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.mma == G->args[i].mma && r.qpl == G->args[i].qpl &&
           r.sel_lut == G->args[i].sel_lut)
         c = (int32_t)j;
     }
@@ -1891,7 +2168,9 @@ void topk_group_destroy(TopkGroup* g) { delete g; }
 extern "C" size_t bs_topk_workspace_size(int64_t nQ, int64_t nC, int32_t N, int32_t k) {
   using namespace bs;
   if (nQ < 0 || nC < 1 || !valid_width(N) || k < 1 || k > BS_MAX_K || k > nC) return 0;
-  return make_plan(nQ, nC, N, k, TopkTune()).total;
+  TopkTune tune;
+  tune.mma = g_mma_override;
+  return make_plan(nQ, nC, N, k, tune).total;
 }
 
 extern "C" int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys) {
@@ -1901,6 +2180,11 @@ extern "C" int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys)
 }
 
 extern "C" int64_t bs_topk_sample_size(int64_t nC) { return nC < 1 ? 0 : bs::sample_rows(nC); }
+
+extern "C" int bs_debug_set_topk_mma(int32_t on) {
+  bs::g_mma_override = on == 0 ? 0 : -1;
+  return 0;
+}
 
 extern "C" int bs_debug_set_topk_tau_rank(int64_t rank) {
   bs::g_taurank_override = rank < 1 ? -1 : rank;
@@ -1917,7 +2201,9 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
     return BS_ERR_ARG;
   if (!C || ((!Q || !out_idx) && nQ > 0)) return BS_ERR_NULL;
   if (nQ > INT32_MAX) return BS_ERR_ARG;
-  Plan p = make_plan(nQ, nC, N, k, TopkTune());
+  TopkTune tune;
+  tune.mma = g_mma_override;
+  Plan p = make_plan(nQ, nC, N, k, tune);
   if (!workspace || workspace_bytes < p.total || (reinterpret_cast<uintptr_t>(workspace) & 255))
     return BS_ERR_WORKSPACE;
   bs_status st = check_device();

@@ -98,6 +98,29 @@ def test_topk_rejects_bad_arguments(lib):
     assert lib.bs_topk_workspace_size(10, 100, 100, 5) == 0
 
 
+def test_topk_plans_for_every_width_and_batch_size(lib):
+    """The host plan (scan mode, slab geometry, workspace layout) for every
+    width, empty and ragged batches and small and large corpora, with the
+    matrix-core scan on and off: a positive size, the same whatever the
+    query count for the per-corpus parts, and no host fault."""
+    from paper_1910_04658_amd.binding import BatchItem
+    widths = [64, 256, 320, 512, 1024, 4096, 8192, 16384]
+    for on in (1, 0):
+        lib.bs_debug_set_topk_mma(on)
+        try:
+            for N in widths:
+                for nQ in (0, 1, 65, 1000):
+                    for nC in (1, 100, 5000, 100_000):
+                        k = min(10, nC)
+                        assert lib.bs_topk_workspace_size(nQ, nC, N, k) > 0, (on, N, nQ, nC)
+        finally:
+            lib.bs_debug_set_topk_mma(1)
+    for N in widths:
+        for nq in (0, 70):
+            it = _batch_item(N=N, n_queries=nq, q_nnz=0 if nq == 0 else 50)
+            assert lib.bs_batch_workspace_size((BatchItem * 1)(it), 1) > 0, (N, nq)
+
+
 def _batch_item(**kw):
     from paper_1910_04658_amd.binding import BatchItem
     it = BatchItem()

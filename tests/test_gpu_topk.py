@@ -68,6 +68,31 @@ def test_scan_path_query_lanes(m, N, nq, dev):
     assert_topk_equal(gi[sel], gs[sel], oi, osc)
 
 
+@pytest.mark.parametrize("m", [oracle.JS, oracle.COS])
+@pytest.mark.parametrize("N,nq", [(512, 70), (1024, 130), (4096, 65), (8192, 20), (16384, 33)])
+def test_vector_and_matrix_scans_agree(m, N, nq, dev):
+    """Widths of whole 512-bit chunks scan on the matrix cores (FP4 products
+    of the sketch bits); with that switched off they take the vector-ALU
+    scans (query lanes, or word-split for N >= 8192). Both give the oracle's
+    result on sampled queries and identical results on all of them."""
+    from paper_1910_04658_amd import binding as bs
+    c = _mid("c20011", lambda: datagen.lognormal_corpus(20011, d=30000, seed=22))
+    w, S = sketch_both(c, N, 6, dev)
+    q = np.linspace(0, 20010, nq).astype(np.int64)
+    Q = w[q.tolist()].contiguous()
+    gi, gs = gpu_topk(Q, w, N, m, 40)
+    try:
+        bs.debug_set_topk_mma(False)
+        vi, vs = gpu_topk(Q, w, N, m, 40)
+    finally:
+        bs.debug_set_topk_mma(True)
+    sel = np.arange(0, nq, max(1, nq // 8))
+    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, N, m, 40)
+    assert_topk_equal(gi[sel], gs[sel], oi, osc)
+    np.testing.assert_array_equal(gi, vi)
+    np.testing.assert_array_equal(gs, vs)
+
+
 @pytest.mark.parametrize("m", [oracle.JS, oracle.HAM])
 @pytest.mark.parametrize("nq", [20, 80])
 def test_overflow_fallback_path(m, nq, dev):
