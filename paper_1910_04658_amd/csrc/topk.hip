@@ -62,7 +62,8 @@ constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the 
 constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, about
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFallbackBlocks = 16;
-constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
+constexpr int kMmaT = 4;             // 16-row MFMA tiles per wave tile of the matrix-core scan
+constexpr int kMmaRows = 16 * kMmaT; // corpus rows per wave tile
 constexpr int kMmaWaves = 16384;     // waves of the matrix-core scan grid, about
 
 struct QConst {  // per-query constants written by the sample pass
@@ -236,7 +237,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.off_qovf = take(nQs * 4);
 
   p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
-  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
+  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * (p.mma ? 4 : 2));
   p.off_ovf = take((nQs + 2) * 4);
   p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
@@ -462,7 +463,7 @@ struct TopkArgs {
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
   uint64_t* __restrict__ scratch;  // [F][nC]
-  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
+  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds (FP32 values for the matrix-core scan)
   int32_t* __restrict__ ovf;       // [2 + nQ]: count, key buffers taken, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
@@ -850,7 +851,8 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
       const int64_t mm = (int64_t)k.xq + xc - X;
       m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
     }
-    a.mtab[(size_t)xc * a.nQp + qi] = m;
+    if (a.mma) reinterpret_cast<float*>(a.mtab)[(size_t)xc * a.nQp + qi] = (float)m;  // compared with FP32 counts
+    else a.mtab[(size_t)xc * a.nQp + qi] = m;
   }
 }
 
@@ -1176,8 +1178,8 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
 // exact counts (N <= 2^24). A and B take the same bit order, so the product
 // is the plain AND-popcount whatever order the unit sums in.
 //
-// A wave owns one 64-query group and the rows of its slab in tiles of 64
-// (4 x 4 MFMA tiles, 64 accumulators per lane); the four waves of a block
+// A wave owns one 64-query group and the rows of its slab in tiles of
+// 16 kMmaT rows (4 x kMmaT MFMA tiles, 16 kMmaT accumulators per lane); the four waves of a block
 // take four query groups of the same slab. The epilogue reads, per lane and
 // 16-query tile, the four consecutive bounds m[x_c][q..q+3] of its row in
 // one 8-byte load; survivors are numbered by wave ballots, no atomics.
@@ -1208,8 +1210,8 @@ template <int KCT>
 __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int i = lane % 16, g = lane / 16;
-  const int64_t sl = bid / a.nqb4;
-  const int64_t qg = (bid % a.nqb4) * (kThreads / kWave) + wid;  // 64-query group
+  const int64_t sl = bid / a.nqb4, qgb = bid % a.nqb4;
+  const int64_t qg = qgb * (kThreads / kWave) + wid;  // 64-query group
   const int64_t c_begin = sl * a.slab;
   const int64_t c_end = c_begin + a.slab < a.nC ? c_begin + a.slab : a.nC;
   if (qg * kWave >= a.nQ || c_begin >= c_end) return;  // wave-uniform
@@ -1238,9 +1240,9 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       qa[qb][1] = p[1];
     }
   };
-  auto load_b = [&](int32_t tile, int ch, uint2 (&cb)[4][2]) {
+  auto load_b = [&](int32_t tile, int ch, uint2 (&cb)[kMmaT][2]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kMmaT; ++t) {
       uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
       r = r < nrows ? r : nrows - 1;
       const uint2* p = reinterpret_cast<const uint2*>(cslab + (r * rowb + 16u * g + 64u * ch));
@@ -1248,16 +1250,16 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       cb[t][1] = p[1];
     }
   };
-  auto load_xc = [&](int32_t tile, int32_t (&xc)[4]) {
+  auto load_xc = [&](int32_t tile, int32_t (&xc)[kMmaT]) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kMmaT; ++t) {
       uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
       r = r < nrows ? r : nrows - 1;
       xc[t] = a.popC[c_begin + r];
     }
   };
-  // bounds of the lane's four queries of each 16-query tile: m[x][qg*64 + 16 qb + 4 g + 0..3]
-  const uint16_t* mcol = a.mtab + qg * kWave + 4 * g;
+  // bounds (FP32) of the lane's four queries of each 16-query tile: m[x][qg*64 + 16 qb + 4 g + 0..3]
+  const float* mcol = reinterpret_cast<const float*>(a.mtab) + qg * kWave + 4 * g;
   const uint32_t stride = (uint32_t)a.stride;
   const int64_t s_end64 = a.S * a.stride < a.nC ? a.S * a.stride : a.nC;
   const uint32_t s_end = (uint32_t)s_end64;
@@ -1287,10 +1289,10 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
     for (int ch = 0; ch < KCT; ++ch) load_a(ch, qh[ch]);
   }
-  uint2 qa[4][2], cb[4][2];
+  uint2 qa[4][2], cb[kMmaT][2];
   if constexpr (!HOLD) load_a(0, qa);
   load_b(0, 0, cb);
-  int32_t xc[4];
+  int32_t xc[kMmaT];
   load_xc(0, xc);
   for (int32_t tile = 0; tile < ntiles; ++tile) {
     if constexpr (HOLD) {  // expand the held words anew per tile (hoisted, they would take 64 registers per chunk)
@@ -1299,9 +1301,9 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) asm volatile("" : "+v"(qh[ch][qb][0]), "+v"(qh[ch][qb][1]));
     }
-    bs_v4f acc[4][4];
+    bs_v4f acc[kMmaT][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < kMmaT; ++t)
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) acc[t][qb] = bs_v4f{0.0f, 0.0f, 0.0f, 0.0f};
     constexpr int KU = KCT > 0 && KCT <= 2 ? KCT : 1;
@@ -1311,7 +1313,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       const bool last = ch + 1 == KC;
       const int32_t nt = last ? (tile + 1 < ntiles ? tile + 1 : tile) : tile;
       const int nch = last ? (tile + 1 < ntiles ? 0 : ch) : ch + 1;
-      uint2 qn[4][2], cn[4][2];
+      uint2 qn[4][2], cn[kMmaT][2];
       if constexpr (!HOLD) load_a(nch, qn);
       load_b(nt, nch, cn);
       auto klass = [&](auto dc) {
@@ -1321,7 +1323,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
         for (int qb = 0; qb < 4; ++qb)
           A[qb] = HOLD ? fp4_class<D>(qh[HOLD ? ch : 0][qb][0], qh[HOLD ? ch : 0][qb][1]) : fp4_class<D>(qa[qb][0], qa[qb][1]);
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < kMmaT; ++t) {
           const bs_v8i B = fp4_class<D>(cb[t][0], cb[t][1]);
 #pragma unroll
           for (int qb = 0; qb < 4; ++qb) acc[t][qb] = mma_class<D>(A[qb], B, acc[t][qb]);
@@ -1337,14 +1339,17 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
           qa[u][0] = qn[u][0];
           qa[u][1] = qn[u][1];
         }
+      }
+#pragma unroll
+      for (int u = 0; u < kMmaT; ++u) {
         cb[u][0] = cn[u][0];
         cb[u][1] = cn[u][1];
       }
     }
     // the next tile's row weights load during this tile's epilogue
-    int32_t xcur[4];
+    int32_t xcur[kMmaT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) xcur[t] = xc[t];
+    for (int t = 0; t < kMmaT; ++t) xcur[t] = xc[t];
     load_xc(tile + 1 < ntiles ? tile + 1 : tile, xc);
     // sampled rows of this tile (scored in the sample pass): one bit per row
     const uint32_t r0 = (uint32_t)(c_begin + (int64_t)tile * kMmaRows);
@@ -1357,30 +1362,32 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       next_s += stride;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kMmaT; ++t) {
       const uint32_t r = r0 + 16 * t + i;
       const bool row_ok = r < r_hi && !((smask >> (16 * t + i)) & 1);
-      const uint16_t* mrow = mcol + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
-      uint2 mt[4];
+      const uint64_t rowm = __builtin_amdgcn_ballot_w64(row_ok);
+      const float* mrow = mcol + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
+      float4 mt[4];
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) mt[qb] = *reinterpret_cast<const uint2*>(mrow + 16 * qb);
+      for (int qb = 0; qb < 4; ++qb) mt[qb] = *reinterpret_cast<const float4*>(mrow + 16 * qb);
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) {
         __builtin_amdgcn_sched_barrier(0);  // one 16-query tile at a time: short live ranges
-        const uint2 mm = mt[qb];
-        const uint32_t m4[4] = {mm.x & 0xffffu, mm.x >> 16, mm.y & 0xffffu, mm.y >> 16};
+        const float m4[4] = {mt[qb].x, mt[qb].y, mt[qb].z, mt[qb].w};
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          const uint32_t x = (uint32_t)acc[t][qb][rr];
-          const bool take = row_ok && x >= m4[rr];  // bounds of queries past the batch are 65535 > N
-          const uint64_t bal = __ballot(take);
+          // counts and bounds are exact integers in FP32; bounds of queries
+          // past the batch are 65535 > N
+          const uint64_t bal = __builtin_amdgcn_ballot_w64(acc[t][qb][rr] >= m4[rr]) & rowm;
           if (bal) {  // wave-uniform
+            const bool take = (bal >> lane) & 1;
             const uint64_t gb = bal & gmask;
             const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(gb >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)gb, 0u));
             const int32_t slot = cnt[qb][rr] + rank;
             if (take && slot < scap)
-              cbase[(size_t)(16 * qb + rr) * a.kmax + (uint32_t)slot * nsl] = raw_entry(x, xcur[t], r, a.N);
+              cbase[(size_t)(16 * qb + rr) * a.kmax + (uint32_t)slot * nsl] =
+                  raw_entry((uint32_t)acc[t][qb][rr], xcur[t], r, a.N);
             cnt[qb][rr] += __popcll(gb);
           }
         }
