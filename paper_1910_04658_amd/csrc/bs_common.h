@@ -10,6 +10,14 @@ namespace bs {
 
 constexpr int kWave = 64;  // CDNA wavefront width
 
+// T(x) = ln(1 - x/N) / ln(1 - 1/N) for x in [0, N] in FP64, with x = N taken as
+// N - 1 (the saturation clamp). Every table of T is built from this one
+// expression, so the FP32 tables of all kernels hold the same bits.
+__device__ __forceinline__ double t_value(int32_t x, int32_t N) {
+  const int32_t xc = x < N ? x : N - 1;
+  return xc == 0 ? 0.0 : log1p(-(double)xc / (double)N) / log1p(-1.0 / (double)N);
+}
+
 // Returns BS_OK if the current device is a gfx950, else BS_ERR_DEVICE.
 bs_status check_device();
 

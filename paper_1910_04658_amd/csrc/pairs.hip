@@ -25,8 +25,7 @@ namespace bs {
 __global__ void build_lut_kernel(int32_t N, double* __restrict__ t64, float* __restrict__ t32) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x > N) return;
-  const int xc = x < N ? x : N - 1;
-  const double v = xc == 0 ? 0.0 : log1p(-(double)xc / (double)N) / log1p(-1.0 / (double)N);
+  const double v = t_value(x, N);
   if (t64) t64[x] = v;
   if (t32) t32[x] = (float)v;
 }

@@ -455,6 +455,7 @@ struct TopkArgs {
   const int32_t* __restrict__ popQ;
   const int32_t* __restrict__ popC;
   QConst* __restrict__ qc;
+  float* __restrict__ t32w;        // null, or: the sample pass builds T itself and stores it here (= t32)
   int32_t* __restrict__ cnts;      // [nQ] sample candidates per query
   uint64_t* __restrict__ cands;    // [nQ][kmax]: S sample candidates (keys), then scap planes of n_slabs
                                    // scan candidates (slot c of slab s at S + c*n_slabs + s; keys from
@@ -490,6 +491,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.popQ = c->popQ;
   a.popC = c->popC;
   a.qc = c->qc;
+  a.t32w = c->t32w;
   a.cnts = c->cnts;
   a.cands = c->cands;
   a.scnt = c->scnt;
@@ -587,7 +589,15 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
   extern __shared__ float lut_s[];
   const float* lut = a.t32;
   if (LDS_LUT) {
-    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    if (a.t32w) {  // small N: every block evaluates T, the first also stores it for the later passes
+      for (int x = threadIdx.x; x <= a.N; x += kThreads) {
+        const float v = (float)t_value(x, a.N);
+        lut_s[x] = v;
+        if (bx == 0 && by == 0) a.t32w[x] = v;
+      }
+    } else {
+      for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    }
     __syncthreads();
     lut = lut_s;
   }
@@ -1963,6 +1973,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.Q = it.Q;
   a.C = it.C;
   a.t32 = it.t32;
+  a.t32w = nullptr;
   a.popQ = it.popQ;
   a.popC = it.popC;
   a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
@@ -2237,10 +2248,12 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   it.t32 = reinterpret_cast<const float*>(ws + p.off_t32);
   TopkArgs a;
   fill_args(a, p, it, ws);
+  if (N <= 1024 && !p.split) a.t32w = reinterpret_cast<float*>(ws + p.off_t32);
   hipStream_t s = as_stream(stream);
   {
     ScopedTiming timing("topk_prep", s);
-    launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
+    // up to N = 1024 the sample pass evaluates T itself (one launch fewer)
+    if (a.t32w == nullptr) launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
     if (!popQ) launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
     if (!popC) launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
   }
