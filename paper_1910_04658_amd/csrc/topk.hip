@@ -237,7 +237,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.off_qovf = take(nQs * 4);
 
   p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
-  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * (p.mma ? 4 : 2));
+  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
   p.off_ovf = take((nQs + 2) * 4);
   p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
@@ -464,7 +464,7 @@ struct TopkArgs {
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
   uint64_t* __restrict__ scratch;  // [F][nC]
-  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds (FP32 values for the matrix-core scan)
+  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
   int32_t* __restrict__ ovf;       // [2 + nQ]: count, key buffers taken, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
@@ -861,8 +861,7 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
       const int64_t mm = (int64_t)k.xq + xc - X;
       m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
     }
-    if (a.mma) reinterpret_cast<float*>(a.mtab)[(size_t)xc * a.nQp + qi] = (float)m;  // compared with FP32 counts
-    else a.mtab[(size_t)xc * a.nQp + qi] = m;
+    a.mtab[(size_t)xc * a.nQp + qi] = m;
   }
 }
 
@@ -1192,7 +1191,8 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
 // 16 kMmaT rows (4 x kMmaT MFMA tiles, 16 kMmaT accumulators per lane); the four waves of a block
 // take four query groups of the same slab. The epilogue reads, per lane and
 // 16-query tile, the four consecutive bounds m[x_c][q..q+3] of its row in
-// one 8-byte load; survivors are numbered by wave ballots, no atomics.
+// one 8-byte LDS read (the tile's bounds are copied to LDS while it is
+// multiplied); survivors are numbered by wave ballots, no atomics.
 typedef int bs_v8i __attribute__((ext_vector_type(8)));
 typedef float bs_v4f __attribute__((ext_vector_type(4)));
 
@@ -1268,8 +1268,25 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       xc[t] = a.popC[c_begin + r];
     }
   };
-  // bounds (FP32) of the lane's four queries of each 16-query tile: m[x][qg*64 + 16 qb + 4 g + 0..3]
-  const float* mcol = reinterpret_cast<const float*>(a.mtab) + qg * kWave + 4 * g;
+  // The bounds of a tile, m[x_c(r)][qg*64 .. qg*64+63] for its 64 rows r (128
+  // bytes each), are copied into the wave's LDS region by eight 16-byte-per-
+  // lane LDS-direct loads issued when the tile starts, so they arrive while
+  // it is multiplied. Load j, lane l: row R = 8 j + l / 8 lands at slot
+  // s = l % 8 and carries piece s ^ (R & 7) of the row (spreads the
+  // epilogue's reads over the banks); x_c(R) comes from lane R % 16, which
+  // holds it in xc[R / 16].
+  __shared__ uint4 mlds[kThreads / kWave][kMmaRows * 8];
+  uint4* const mw = mlds[wid];
+  const uint16_t* const mq = a.mtab + qg * kWave;
+  auto bounds_to_lds = [&](const int32_t (&xt)[kMmaT]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t R = 8u * j + lane / 8, piece = (lane % 8) ^ (R & 7);
+      const int32_t x = __shfl(xt[j / 2], (int)(R % 16));
+      const uint16_t* src = mq + (size_t)(uint32_t)x * (size_t)a.nQp + 8 * piece;
+      __builtin_amdgcn_global_load_lds(src, mw + 64 * j, 16, 0, 0);
+    }
+  };
   const uint32_t stride = (uint32_t)a.stride;
   const int64_t s_end64 = a.S * a.stride < a.nC ? a.S * a.stride : a.nC;
   const uint32_t s_end = (uint32_t)s_end64;
@@ -1304,7 +1321,16 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   load_b(0, 0, cb);
   int32_t xc[kMmaT];
   load_xc(0, xc);
+  // With four or more chunks a tile is long enough to hide the copy of its
+  // bounds; shorter ones read them from the table in the epilogue.
+  constexpr bool LDSB = KCT == 0 || KCT >= 4;
   for (int32_t tile = 0; tile < ntiles; ++tile) {
+    if constexpr (LDSB) {
+      // the previous epilogue's reads of the region are done (their values
+      // were used); then this tile's bounds start their way into it
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      bounds_to_lds(xc);
+    }
     if constexpr (HOLD) {  // expand the held words anew per tile (hoisted, they would take 64 registers per chunk)
 #pragma unroll
       for (int ch = 0; ch < (HOLD ? KCT : 1); ++ch)
@@ -1361,6 +1387,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
 #pragma unroll
     for (int t = 0; t < kMmaT; ++t) xcur[t] = xc[t];
     load_xc(tile + 1 < ntiles ? tile + 1 : tile, xc);
+    if constexpr (LDSB) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this tile's bounds are in LDS
     // sampled rows of this tile (scored in the sample pass): one bit per row
     const uint32_t r0 = (uint32_t)(c_begin + (int64_t)tile * kMmaRows);
     const uint32_t r_hi = (uint32_t)(c_begin + (int64_t)tile * kMmaRows + kMmaRows < c_end
@@ -1376,14 +1403,20 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       const uint32_t r = r0 + 16 * t + i;
       const bool row_ok = r < r_hi && !((smask >> (16 * t + i)) & 1);
       const uint64_t rowm = __builtin_amdgcn_ballot_w64(row_ok);
-      const float* mrow = mcol + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
-      float4 mt[4];
+      const uint32_t R = 16u * t + i;
+      uint2 mg[4];
+      if constexpr (!LDSB) {
+        const uint16_t* mrow = mq + 4 * g + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) mt[qb] = *reinterpret_cast<const float4*>(mrow + 16 * qb);
+        for (int qb = 0; qb < 4; ++qb) mg[qb] = *reinterpret_cast<const uint2*>(mrow + 16 * qb);
+      }
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) {
         __builtin_amdgcn_sched_barrier(0);  // one 16-query tile at a time: short live ranges
-        const float m4[4] = {mt[qb].x, mt[qb].y, mt[qb].z, mt[qb].w};
+        // LDS: queries 16 qb + 4 g .. +3 are piece 2 qb + g / 2 of row R, half g % 2
+        const uint32_t sl8 = (2u * qb + g / 2) ^ (R & 7);
+        const uint2 m2 = LDSB ? reinterpret_cast<const uint2*>(mw + R * 8 + sl8)[g & 1] : mg[qb];
+        const float m4[4] = {(float)(m2.x & 0xffffu), (float)(m2.x >> 16), (float)(m2.y & 0xffffu), (float)(m2.y >> 16)};
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
           // counts and bounds are exact integers in FP32; bounds of queries
