@@ -1190,9 +1190,9 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
 // A wave owns one 64-query group and the rows of its slab in tiles of
 // 16 kMmaT rows (4 x kMmaT MFMA tiles, 16 kMmaT accumulators per lane); the four waves of a block
 // take four query groups of the same slab. The epilogue reads, per lane and
-// 16-query tile, the four consecutive bounds m[x_c][q..q+3] of its row in
-// one 8-byte LDS read (the tile's bounds are copied to LDS while it is
-// multiplied); survivors are numbered by wave ballots, no atomics.
+// row, the bounds m[x_c][q] of its 16 queries, one 32-byte run of the table
+// row (for four or more chunks copied to LDS while the tile is multiplied);
+// survivors are numbered by wave ballots, no atomics.
 typedef int bs_v8i __attribute__((ext_vector_type(8)));
 typedef float bs_v4f __attribute__((ext_vector_type(4)));
 
@@ -1235,10 +1235,14 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const char* qbase = reinterpret_cast<const char*>(a.Q) + (size_t)qg * kWave * rowb;
   const char* cslab = reinterpret_cast<const char*>(a.C) + (size_t)c_begin * rowb;
   const uint32_t nrows = (uint32_t)(c_end - c_begin);
+  // Query order: row i of 16-query tile qb is query 16 (i / 4) + 4 qb + i % 4
+  // of the group, so the 16 queries whose counts a lane of group g holds
+  // (result rows 4 g .. 4 g + 3 of every tile) are the consecutive queries
+  // 16 g .. 16 g + 15, and their bounds are one 32-byte run of a table row.
   uint32_t qoff[4];
 #pragma unroll
   for (int qb = 0; qb < 4; ++qb) {
-    int64_t q = qg * kWave + 16 * qb + i;
+    int64_t q = qg * kWave + 16 * (i / 4) + 4 * qb + i % 4;
     q = q < a.nQ ? q : a.nQ - 1;
     qoff[qb] = (uint32_t)(q - qg * kWave) * rowb + 16u * g;
   }
@@ -1292,11 +1296,11 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const uint32_t s_end = (uint32_t)s_end64;
   // first sampled row at or after the slab start (rows past s_end are never sampled)
   uint32_t next_s = (uint32_t)((c_begin + a.stride - 1) / a.stride * a.stride);
-  // Survivors of query (qb, g, rr) = qg*64 + 16 qb + 4 g + rr are numbered by
+  // Survivors of query (qb, g, rr) = qg*64 + 16 g + 4 qb + rr are numbered by
   // a ballot over the 16 lanes of group g; cnt[qb][rr] holds the group's
   // running count (the same in its 16 lanes). Slot s of that query lies at
-  // cbase + (16 qb + rr) * kmax + s * n_slabs.
-  uint64_t* const cbase = a.cands + (size_t)(qg * kWave + 4 * g) * a.kmax + a.S + sl;
+  // cbase + (4 qb + rr) * kmax + s * n_slabs.
+  uint64_t* const cbase = a.cands + (size_t)(qg * kWave + 16 * g) * a.kmax + a.S + sl;
   const int32_t scap = (int32_t)a.scap;
   const uint32_t nsl = (uint32_t)a.n_slabs;
   const uint64_t gmask = 0xffffull << (16 * g);
@@ -1404,18 +1408,21 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       const bool row_ok = r < r_hi && !((smask >> (16 * t + i)) & 1);
       const uint64_t rowm = __builtin_amdgcn_ballot_w64(row_ok);
       const uint32_t R = 16u * t + i;
-      uint2 mg[4];
-      if constexpr (!LDSB) {
-        const uint16_t* mrow = mq + 4 * g + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp;
-#pragma unroll
-        for (int qb = 0; qb < 4; ++qb) mg[qb] = *reinterpret_cast<const uint2*>(mrow + 16 * qb);
+      // bounds of queries 16 g .. 16 g + 15 for this row: pieces 2 g and 2 g + 1
+      uint4 mg[2];
+      if constexpr (LDSB) {
+        mg[0] = mw[R * 8 + ((2u * g) ^ (R & 7))];
+        mg[1] = mw[R * 8 + ((2u * g + 1) ^ (R & 7))];
+      } else {
+        const uint4* mrow =
+            reinterpret_cast<const uint4*>(mq + 16 * g + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp);
+        mg[0] = mrow[0];
+        mg[1] = mrow[1];
       }
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) {
         __builtin_amdgcn_sched_barrier(0);  // one 16-query tile at a time: short live ranges
-        // LDS: queries 16 qb + 4 g .. +3 are piece 2 qb + g / 2 of row R, half g % 2
-        const uint32_t sl8 = (2u * qb + g / 2) ^ (R & 7);
-        const uint2 m2 = LDSB ? reinterpret_cast<const uint2*>(mw + R * 8 + sl8)[g & 1] : mg[qb];
+        const uint2 m2 = (qb & 1) ? make_uint2(mg[qb / 2].z, mg[qb / 2].w) : make_uint2(mg[qb / 2].x, mg[qb / 2].y);
         const float m4[4] = {(float)(m2.x & 0xffffu), (float)(m2.x >> 16), (float)(m2.y & 0xffffu), (float)(m2.y >> 16)};
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -1429,7 +1436,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)gb, 0u));
             const int32_t slot = cnt[qb][rr] + rank;
             if (take && slot < scap)
-              cbase[(size_t)(16 * qb + rr) * a.kmax + (uint32_t)slot * nsl] =
+              cbase[(size_t)(4 * qb + rr) * a.kmax + (uint32_t)slot * nsl] =
                   raw_entry((uint32_t)acc[t][qb][rr], xcur[t], r, a.N);
             cnt[qb][rr] += __popcll(gb);
           }
@@ -1437,17 +1444,14 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       }
     }
   }
-  // lane l reports query qg*64 + l = (qb, g', rr) = (l / 16, (l % 16) / 4, l % 4),
-  // whose count sits in every lane of group g'
+  // lane l reports query qg*64 + l = (g, qb, rr) = (l / 16, (l % 16) / 4, l % 4),
+  // a query of its own group
   int32_t n = 0;
-  const int src = 16 * ((lane % 16) / 4);
 #pragma unroll
   for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int32_t v = __shfl(cnt[qb][rr], src);
-      if (qb == lane / 16 && rr == lane % 4) n = v;
-    }
+    for (int rr = 0; rr < 4; ++rr)
+      if (qb == i / 4 && rr == i % 4) n = cnt[qb][rr];
   const int64_t q = qg * kWave + lane;
   if (q < a.nQ) {
     a.scnt[(size_t)q * a.n_slabs + sl] = n < scap ? n : scap;
