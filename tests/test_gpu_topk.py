@@ -135,24 +135,26 @@ def test_failed_tau_check_falls_back(m, nq, dev):
         assert_topk_equal(gi[sel], gs[sel], oi, osc)
 
 
+@pytest.mark.parametrize("N", [256, 1024])
 @pytest.mark.parametrize("lds_keys", [None, 0, 1024])
 @pytest.mark.parametrize("nq", [9, 70])
-def test_large_candidate_sets_compact_in_place(lds_keys, nq, dev):
+def test_large_candidate_sets_compact_in_place(N, lds_keys, nq, dev):
     """Candidate sets above the LDS buffer are compacted and selected in
     place in global memory. k = 1000 over 60k rows gives ~15k candidates per
     query; the LDS limit is also forced down to send every query (0) or
-    most (1024) through the in-place path, for both scan modes (9 queries:
-    row lanes, 70: query lanes)."""
+    most (1024) through the in-place path, for every scan mode (9 queries:
+    row lanes; 70: query lanes at N = 256, the matrix cores at N = 1024,
+    with many survivors per slab)."""
     from paper_1910_04658_amd import binding as bs
     c = _mid("c60k", lambda: datagen.lognormal_corpus(60000, d=50000, seed=26))
-    w, S = sketch_both(c, 256, 10, dev)
+    w, S = sketch_both(c, N, 10, dev)
     q = np.linspace(0, 59999, nq).astype(np.int64)
     sel = np.arange(0, nq, max(1, nq // 9))
-    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, 256, oracle.JS, 1000)
+    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, N, oracle.JS, 1000)
     try:
         if lds_keys is not None:
             bs.debug_set_topk_limits(lds_keys=lds_keys)
-        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, 256, oracle.JS, 1000)
+        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, N, oracle.JS, 1000)
     finally:
         bs.debug_set_topk_limits()
     assert_topk_equal(gi[sel], gs[sel], oi, osc)
