@@ -803,7 +803,7 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
 // non-decreasing that means x_u <= X = max{x : T(x) <= bound}, i.e.
 //   x_ab >= m[x_c][q] = x_q + x_c - X.
 // m is clamped to [0, 65535]: lowering it only admits more candidates.
-constexpr int kBoundX = 64;  // table rows (x_c values) per block of the threshold kernel
+constexpr int kBoundX = 16;  // table rows (x_c values) per block of the threshold kernel
 
 template <int M, bool LDS_LUT>
 __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_t by) {
