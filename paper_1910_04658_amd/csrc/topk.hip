@@ -1,8 +1,8 @@
 // Query-vs-corpus top-k by estimated similarity on gfx950.
 //
 // For every query sketch and every corpus sketch the pair count
-// x_ab = |q_s AND c_s| (Algorithm 1, second step) is formed on the vector ALU
-// and turned into the FP32 score of the chosen measure (Algorithms 1-4, the
+// x_ab = |q_s AND c_s| (Algorithm 1, second step) is formed on the matrix
+// cores or the vector ALU and turned into the FP32 score of the chosen measure (Algorithms 1-4, the
 // canonical form documented in binsketch.h). The k best corpus rows per query
 // are returned ordered by (score, then smaller index). The paper ranks by a
 // similarity threshold (Section 4.2); a fixed k is the serving form of it.
@@ -16,12 +16,15 @@
 //     probability below 1e-9 (a Poisson tail; kt = k when the sample is the
 //     corpus), so tau is almost always <= the true k-th best score and the
 //     candidates are about kt * nC / S rather than k * nC / S.
-//  2. scan: every other (query, corpus row) pair. Lanes hold queries (words in
-//     VGPRs), corpus rows arrive on the scalar unit. Instead of evaluating the
-//     score (an IEEE division per pair) the kernel tests x_ab >= m[x_c][q], a
-//     per-query integer bound that every pair scoring >= tau satisfies. Each
-//     lane writes its survivors (a few percent) into the query's own slot
-//     range for that corpus slab, counted in a register: no atomics.
+//  2. scan: every other (query, corpus row) pair. For N a multiple of 512 the
+//     pair counts of a query batch against the corpus are formed on the
+//     matrix cores as a product of 0/1 matrices (FP4 operands, exact FP32
+//     counts); otherwise lanes hold queries (words in VGPRs) and corpus rows
+//     arrive on the scalar unit. Instead of evaluating the score (an IEEE
+//     division per pair) both test x_ab >= m[x_c][q], a per-query integer
+//     bound that every pair scoring >= tau satisfies, and write the survivors
+//     (a few percent) into the query's own slot range for that corpus slab,
+//     numbered without atomics.
 //  3. select: per query, the sample and slab candidates are compacted (block
 //     scan over slab counts), scored exactly as unique 64-bit keys (score
 //     key, then inverted index), the k-th key found by radix select and the
