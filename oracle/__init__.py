@@ -65,7 +65,6 @@ def lib():
             L.orc_score_f32.restype = ctypes.c_float
             L.orc_estimate_pairs.argtypes = [p, i64, p, i64, p, i32, p]
             L.orc_topk.argtypes = [p, p, p, i64, p, p, p, i64, i32, ctypes.c_int, i32, p, p]
-            L.orc_scores_f32.argtypes = [p, p, p, i64, p, p, p, i64, i32, ctypes.c_int, p]
             _lib = L
     return _lib
 
@@ -192,14 +191,6 @@ def topk(Q: Sets, C: Sets, N: int, measure: int, k: int):
     if rc:
         raise ValueError("oracle: bad top-k arguments")
     return idx, sc
-
-
-def scores_f32(Q: Sets, C: Sets, N: int, measure: int) -> np.ndarray:
-    out = np.zeros((Q.n, C.n), np.float32)
-    lib().orc_scores_f32(_ptr(Q.vals), _ptr(Q.start), _ptr(Q.length), Q.n,
-                         _ptr(C.vals), _ptr(C.start), _ptr(C.length), C.n,
-                         int(N), int(measure), _ptr(out))
-    return out
 
 
 # ---------------------------------------------------------------------------

@@ -336,16 +336,3 @@ int orc_topk(const int32_t* q_vals, const int32_t* q_start, const int32_t* q_len
   }
   return err;
 }
-
-/* FP32 scores of every (query, corpus) pair, for threshold checks in tests. */
-int orc_scores_f32(const int32_t* q_vals, const int32_t* q_start, const int32_t* q_len, int64_t nQ,
-                   const int32_t* c_vals, const int32_t* c_start, const int32_t* c_len, int64_t nC,
-                   int32_t N, int measure, float* out) {
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t p = 0; p < nQ; ++p)
-    for (int64_t q = 0; q < nC; ++q) {
-      int64_t xab = merge_count(q_vals + q_start[p], q_len[p], c_vals + c_start[q], c_len[q]);
-      out[p * nC + q] = orc_score_f32(q_len[p], c_len[q], xab, N, measure);
-    }
-  return ORC_OK;
-}

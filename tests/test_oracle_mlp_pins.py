@@ -90,3 +90,58 @@ def test_adam_matches_torch():
         t.grad = torch.tensor(g, dtype=torch.float64)
         opt.step()
     np.testing.assert_allclose(theta, t.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_bf16_gradient_against_autograd():
+    """The BF16 path of the oracle's hand-written backpropagation against
+    torch autograd in FP64 on the CPU, with the roundings written as
+    straight-through steps: h1 is rounded to BF16 on the way forward (its
+    gradient passes unchanged), and the gradient reaching the layer-2 product
+    from z2 is rounded to BF16 on the way back (b2 takes it unrounded). That
+    is the model the rounding points define; autograd differentiates it
+    independently of the oracle's own chain rule."""
+    torch = pytest.importorskip("torch")
+
+    def bf16(t):
+        return torch.from_numpy(mlp.bf16_round(t.detach().numpy()))
+
+    class RoundForward(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            return bf16(x)
+
+        @staticmethod
+        def backward(ctx, g):
+            return g
+
+    class RoundBackward(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, x):
+            return x.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return bf16(g)
+
+    rng = np.random.default_rng(6)
+    N = 256
+    xa, xb, xab = _counts(rng, 300, N)
+    label = rng.random(300)
+    theta = _random_theta(rng, 0.4)
+    base = mlp.closed_form(xa, xb, xab, N)
+    loss, g = mlp.loss_and_grad(theta, xa, xb, xab, label, N, bf16=True, base=base)
+    P = {k: torch.tensor(np.array(v, np.float64), requires_grad=True) for k, v in mlp.unpack(theta).items()}
+    f = torch.from_numpy(mlp.features(xa, xb, xab, N))
+    z1 = f @ P["W1"].T + P["b1"]
+    h1q = RoundForward.apply(torch.relu(z1))
+    z2 = RoundBackward.apply(h1q @ P["W2"].T) + P["b2"]
+    y = torch.relu(z2) @ P["w3"] + P["b3"]
+    p = torch.from_numpy(base) + y
+    L = torch.mean((p - torch.from_numpy(label)) ** 2)
+    L.backward()
+    ref = mlp.pack({k: v.grad.numpy() for k, v in P.items()})
+    assert abs(float(L) - loss) <= 1e-12 * loss
+    np.testing.assert_allclose(g, ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    # the rounding matters: the smooth model's gradient differs
+    _, g_smooth = mlp.loss_and_grad(theta, xa, xb, xab, label, N, bf16=False, base=base)
+    assert np.abs(g_smooth - ref).max() > 1e-6 * np.abs(ref).max()

@@ -190,6 +190,57 @@ def test_lemma2_concentration_failure_rate():
     assert fails / trials <= delta
 
 
+def test_lemma3_concentration_failure_rate():
+    """Lemma 3: |<a_s, b_s> - E<a_s, b_s>| < sqrt(psi/2 ln(2/delta)) fails with
+    probability at most delta, for |a|, |b| <= psi. The expectation is Lemma 1
+    part 2 with the -IP exponent; the +IP exponent printed on its last line
+    puts the mean outside the bound in almost every trial."""
+    rng = np.random.default_rng(10)
+    d, N, psi, delta = 400, 256, 100, 0.05
+    a = np.arange(0, 100)
+    b = np.arange(60, 160)  # |a n b| = 40
+    ip, ix = _rows_csr([a, b], d)
+    bound = math.sqrt(psi / 2 * math.log(2 / delta))
+    n = 1 - 1 / N
+    e_minus = N * (1 - 2 * n ** 100 + n ** (200 - 40))
+    e_plus = N * (1 - 2 * n ** 100 + n ** (200 + 40))
+    fails = fails_plus = 0
+    trials = 2000
+    for _ in range(trials):
+        pi = rng.integers(0, N, d).astype(np.int32)
+        S = oracle.sketch_sets(ip, ix, d, pi, N)
+        x = int(oracle.intersections(S, S)[0, 1])
+        fails += abs(x - e_minus) >= bound
+        fails_plus += abs(x - e_plus) >= bound
+    assert fails / trials <= delta
+    assert fails_plus / trials > 0.9
+
+
+# --- the random map: uniform over the N^d functions (Definition BinSketch) ---------
+
+@pytest.mark.parametrize("N,seed", [(64, 1), (1024, 2), (4096, 3)])
+def test_random_map_is_uniform(N, seed):
+    """Chi-square tests of the map generator: the values of pi are uniform on
+    [0, N) and consecutive coordinates are independent (pairs uniform on
+    [0, N)^2 for the low 5 bits), as a map drawn uniformly from the N^d
+    functions must be."""
+    from scipy.stats import chi2
+    d = 100 * N
+    pi = datagen.random_map(d, N, seed)
+    assert pi.dtype == np.int32 and pi.min() >= 0 and pi.max() < N
+    cnt = np.bincount(pi, minlength=N)
+    e = d / N
+    stat = float(((cnt - e) ** 2 / e).sum())
+    p = chi2.sf(stat, N - 1)
+    assert 1e-4 < p < 1 - 1e-4, (stat, p)
+    lo = (pi & 31).astype(np.int64)
+    cells = np.bincount(lo[0::2] * 32 + lo[1::2], minlength=1024)
+    e2 = (d // 2) / 1024
+    stat2 = float(((cells - e2) ** 2 / e2).sum())
+    p2 = chi2.sf(stat2, 1023)
+    assert 1e-4 < p2 < 1 - 1e-4, (stat2, p2)
+
+
 # --- Algorithm 1-4: the estimators ------------------------------------------------
 
 def test_algorithm1_inverts_lemma1():
@@ -258,6 +309,33 @@ def test_saturation_rule():
         assert abs(e[0] - (T(xb) if xb else 0.0)) < 1e-9
     e = oracle.estimate(N, N, N, N)
     assert np.all(np.isfinite(e)) and abs(e[2] - 1) < 1e-12
+
+
+def test_estimate_pairs_planes_and_strides():
+    """The dense FP64 form writes plane m, row p, column q of a [4][nA][nB]
+    array with the per-pair canonical estimate of (x_a[p], x_b[q], x_ab[p][q]);
+    a non-square shape with counts that differ in every row and column exposes a
+    swapped plane, row or stride. Unsaturated pairs also match Algorithm 1 as
+    printed (with the Hamming factor 2)."""
+    rng = np.random.default_rng(17)
+    N, nA, nB = 1024, 37, 53
+    xa = rng.integers(0, N + 1, nA).astype(np.int32)
+    xb = rng.integers(0, N + 1, nB).astype(np.int32)
+    xa[:3] = [0, N, N - 1]
+    xb[:3] = [N, 0, 1]
+    lo = np.maximum(0, xa[:, None] + xb[None, :] - N)
+    hi = np.minimum(xa[:, None], xb[None, :])
+    xab = (lo + (rng.random((nA, nB)) * (hi - lo + 1)).astype(np.int64)).astype(np.int32)
+    out = oracle.estimate_pairs(xa, xb, xab, N)
+    assert out.shape == (4, nA, nB)
+    for p in range(nA):
+        for q in range(nB):
+            ref = oracle.estimate(xa[p], xb[q], xab[p, q], N)
+            assert np.array_equal(out[:, p, q], ref), (p, q)
+            if 0 < xa[p] < N and 0 < xb[q] < N and xa[p] + xb[q] - xab[p, q] < N:
+                lit = oracle.estimate_literal(xa[p], xb[q], xab[p, q], N)
+                np.testing.assert_allclose(out[:, p, q], lit, rtol=1e-9,
+                                           atol=1e-9 * max(1.0, abs(lit[0]), abs(lit[1])))
 
 
 def test_score_f32_tracks_fp64():
