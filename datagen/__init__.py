@@ -272,6 +272,41 @@ def lognormal_corpus(n: int, d: int = 100_000, mean: float = 230.0, sd: float = 
     return gen(rng, lengths, d, 1.1)
 
 
+def identity_map(N: int) -> np.ndarray:
+    """pi(i) = i on [N]: with d = N every row is its own sketch."""
+    return np.arange(N, dtype=np.int32)
+
+
+def saturation_rows(n: int, N: int, seed: int, p_empty: float = 0.03, p_full: float = 0.03,
+                    p_near: float = 0.06, len_hi: int = 4096, last_full: bool = False) -> CSR:
+    """n rows over [0, N), meant for the identity map (d = N), so that their
+    sketches are chosen directly: a mix of empty rows, full rows (all N
+    coordinates), rows missing 1-8 coordinates, and rows whose length is
+    log-uniform on [1, min(len_hi, N)] with uniform distinct coordinates.
+    The empty and full rows drive the 0/0 and x = N (saturation) cases of the
+    estimators; ``last_full`` makes the last row full."""
+    rng = np.random.default_rng(seed)
+    kind = rng.choice(4, size=n, p=[p_empty, p_full, p_near, 1.0 - p_empty - p_full - p_near])
+    if last_full and n > 0:
+        kind[-1] = 1
+    hi = min(len_hi, N)
+    rows = []
+    for r in range(n):
+        if kind[r] == 0:
+            rows.append(np.zeros(0, np.int64))
+        elif kind[r] == 1:
+            rows.append(np.arange(N, dtype=np.int64))
+        elif kind[r] == 2:
+            holes = rng.choice(N, size=int(rng.integers(1, 9)), replace=False)
+            keep = np.ones(N, bool)
+            keep[holes] = False
+            rows.append(np.nonzero(keep)[0])
+        else:
+            m = int(np.exp(rng.uniform(0.0, np.log(hi))))
+            rows.append(np.sort(rng.choice(N, size=max(m, 1), replace=False)))
+    return from_rows(rows, N)
+
+
 def planted_pairs(rng: np.random.Generator, base: CSR, frac: np.ndarray, s: float = 1.1) -> CSR:
     """For each row a of ``base``, a partner b = a with a fraction frac[r] of its ids
     replaced by fresh Zipf(s)-popular ids not already in a (near-duplicate pairs)."""

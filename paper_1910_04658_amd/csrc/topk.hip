@@ -1232,8 +1232,8 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const int32_t ntiles = (int32_t)((c_end - c_begin + kMmaRows - 1) / kMmaRows);
   // Operands are read as a uniform base (scalar registers) plus a 32-bit lane
   // offset. A rows: query qg*64 + 16 qb + i (past the batch: the last query,
-  // masked later by its bound); B rows: tile row 16 t + i (past the slab: its
-  // last row, masked in the epilogue).
+  // whose lanes are masked out of every survivor ballot); B rows: tile row
+  // 16 t + i (past the slab: its last row, masked in the epilogue).
   const uint32_t rowb = (uint32_t)W32 * 4u;  // bytes per row
   const char* qbase = reinterpret_cast<const char*>(a.Q) + (size_t)qg * kWave * rowb;
   const char* cslab = reinterpret_cast<const char*>(a.C) + (size_t)c_begin * rowb;
@@ -1307,6 +1307,16 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const int32_t scap = (int32_t)a.scap;
   const uint32_t nsl = (uint32_t)a.n_slabs;
   const uint64_t gmask = 0xffffull << (16 * g);
+  // Lanes whose query (qb, g, rr) lies inside the batch: query 16 g + 4 qb + rr
+  // of the group exists iff g < ceil((nrem - 4 qb - rr) / 16). Queries past the
+  // batch hold the last real query's words and must never store a survivor,
+  // whatever their bound (a count can reach the 16-bit bound at N = 65536).
+  const int32_t nrem = (int32_t)(a.nQ - qg * kWave < kWave ? a.nQ - qg * kWave : kWave);
+  auto qvalid = [&](int qb, int rr) -> uint64_t {
+    const int32_t c = nrem - 4 * qb - rr;
+    const int32_t ng = c <= 0 ? 0 : ((c + 15) / 16 < 4 ? (c + 15) / 16 : 4);
+    return ng >= 4 ? ~0ull : ((1ull << (16 * ng)) - 1ull);
+  };
   int32_t cnt[4][4];
 #pragma unroll
   for (int qb = 0; qb < 4; ++qb)
@@ -1429,9 +1439,8 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
         const float m4[4] = {(float)(m2.x & 0xffffu), (float)(m2.x >> 16), (float)(m2.y & 0xffffu), (float)(m2.y >> 16)};
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
-          // counts and bounds are exact integers in FP32; bounds of queries
-          // past the batch are 65535 > N
-          const uint64_t bal = __builtin_amdgcn_ballot_w64(acc[t][qb][rr] >= m4[rr]) & rowm;
+          // counts and bounds are exact integers in FP32
+          const uint64_t bal = __builtin_amdgcn_ballot_w64(acc[t][qb][rr] >= m4[rr]) & rowm & qvalid(qb, rr);
           if (bal) {  // wave-uniform
             const bool take = (bal >> lane) & 1;
             const uint64_t gb = bal & gmask;

@@ -104,7 +104,7 @@ def test_topk_plans_for_every_width_and_batch_size(lib):
     matrix-core scan on and off: a positive size, the same whatever the
     query count for the per-corpus parts, and no host fault."""
     from paper_1910_04658_amd.binding import BatchItem
-    widths = [64, 256, 320, 512, 1024, 4096, 8192, 16384]
+    widths = [64, 256, 320, 512, 1024, 4096, 8192, 16384, 32768, 65536]
     for on in (1, 0):
         lib.bs_debug_set_topk_mma(on)
         try:
