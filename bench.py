@@ -255,7 +255,7 @@ def jaccard_mse(step, corpus, queries):
 
 
 def ranking_eval(dev, max_queries=500, widths=(256, 1024, 4096)):
-    """Threshold retrieval (Section 5, Experiment 2) on synthetic rows with
+    """Threshold retrieval (Section 4.2, Experiment 2) on synthetic rows with
     planted near-duplicates, split 90/10 into corpus and queries: for every
     query the corpus rows whose similarity reaches each of the paper's
     thresholds, from bs_estimate on the sketches against the exact

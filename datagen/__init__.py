@@ -466,7 +466,7 @@ def concat_rows(a: CSR, b: CSR) -> CSR:
 
 def ranking_split(n_background: int = 20_000, n_groups: int = 1000, group_size: int = 10, d: int = 100_000,
                   seed: int = SEED_RANKING, query_frac: float = 0.1):
-    """Data of the ranking experiment (Section 5, Experiment 2) on synthetic
+    """Data of the ranking experiment (Section 4.2, Experiment 2) on synthetic
     rows: `n_background` rows of the benchmark distribution plus `n_groups`
     groups of `group_size` near-duplicates (variant_groups), so that exact
     similarities reach the high thresholds, shuffled and split into a

@@ -1,6 +1,6 @@
 """Threshold-retrieval quality — CPU oracle (TEST INFRASTRUCTURE ONLY).
 
-The ranking experiment of Section 5 (Experiment 2): for every query, O is the
+The ranking experiment of Section 4.2 (Experiment 2): for every query, O is the
 set of corpus points whose exact similarity reaches a threshold and O' the set
 whose similarity estimated from the sketches does. The paper scores O' against
 O by

@@ -339,12 +339,14 @@ __global__ void mlp_reduce_kernel(const float* __restrict__ partial, int32_t n_w
 // Adam on the FP32 master weights, then the BF16 copy.
 __global__ void mlp_adam_kernel(float* __restrict__ theta, uint16_t* __restrict__ wb, float* __restrict__ m,
                                 float* __restrict__ v, const float* __restrict__ grad, float lr, float beta1,
-                                float beta2, float eps, float c1, float c2) {
+                                float omb1, float beta2, float omb2, float eps, float c1, float c2) {
+  // omb1 = 1 - beta1 and omb2 = 1 - beta2 come rounded from double: formed in
+  // FP32 from the rounded betas, 1 - beta2 would be off by 1.3e-5 relative
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NP) return;
   const float g = grad[p];
-  const float mm = beta1 * m[p] + (1.0f - beta1) * g;
-  const float vv = beta2 * v[p] + (1.0f - beta2) * g * g;
+  const float mm = beta1 * m[p] + omb1 * g;
+  const float vv = beta2 * v[p] + omb2 * g * g;
   m[p] = mm;
   v[p] = vv;
   const float th = theta[p] - lr * (mm * c1) / (sqrtf(vv * c2) + eps);
@@ -480,7 +482,7 @@ extern "C" bs_status bs_mlp_train_step(float* master, uint16_t* w, float* adam_m
   const float c1 = (float)(1.0 / (1.0 - pow(b1, (double)step)));
   const float c2 = (float)(1.0 / (1.0 - pow(b2, (double)step)));
   hipLaunchKernelGGL(mlp_adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, s, master, w, adam_m, adam_v, grad,
-                     lr, (float)b1, (float)b2, 1e-8f, c1, c2);
+                     lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), 1e-8f, c1, c2);
   return launch_status();
 }
 

@@ -1,4 +1,4 @@
-"""Threshold-retrieval quality of the sketch estimates (Section 5, Experiment 2).
+"""Threshold-retrieval quality of the sketch estimates (Section 4.2, Experiment 2).
 
 For every query, O holds the corpus rows whose exact similarity reaches a
 threshold and O' those whose estimated similarity (bs_estimate on the

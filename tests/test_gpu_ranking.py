@@ -1,4 +1,4 @@
-"""Threshold retrieval (Section 5, Experiment 2) from GPU estimates against
+"""Threshold retrieval (Section 4.2, Experiment 2) from GPU estimates against
 the oracle: the pairs found at each threshold from bs_estimate equal those
 found from the oracle's FP64 estimates (a pair may differ only where the
 oracle's estimate is within the FP64 tolerance of the threshold), and the

@@ -1,4 +1,4 @@
-"""Threshold-retrieval metrics (Section 5, Experiment 2): the oracle's
+"""Threshold-retrieval metrics (Section 4.2, Experiment 2): the oracle's
 plain-set definitions pinned by hand-computed cases, and the library's
 vectorised version checked against the oracle."""
 import numpy as np
