@@ -12,7 +12,9 @@
  *   - All data pointers are DEVICE pointers on the current HIP device,
  *     allocated and owned by the caller. The library allocates no device
  *     memory and keeps no state between calls apart from a per-device check
- *     that the device is a gfx950 (and the host-side batch handles, below).
+ *     that the device is a gfx950, the host-side batch handles (below) and
+ *     the fixed scratch array of bs_estimate_noalloc (a static device array of
+ *     BS_NOALLOC_SCRATCH_BYTES per GPU, loaded with the library's code).
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Every call only enqueues work on that stream and returns before the
  *     work completes; results are valid once the stream has been synchronised.
@@ -44,7 +46,9 @@ typedef enum {
   BS_ERR_ARG = 2,       /* a size or parameter is out of range */
   BS_ERR_WORKSPACE = 3, /* the workspace is NULL or smaller than required */
   BS_ERR_HIP = 4,       /* the HIP runtime rejected a launch */
-  BS_ERR_DEVICE = 5     /* the current device is not a gfx950 */
+  BS_ERR_DEVICE = 5,    /* the current device is not a gfx950 */
+  BS_ERR_SCRATCH = 6    /* the call needs more than BS_NOALLOC_SCRATCH_BYTES of
+                           fixed scratch (bs_estimate_noalloc) */
 } bs_status;
 
 typedef enum { BS_IP = 0, BS_HAMMING = 1, BS_JACCARD = 2, BS_COSINE = 3 } bs_measure;
@@ -172,6 +176,29 @@ bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const 
                       const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
                       double* js, double* cos, void* workspace, size_t workspace_bytes,
                       void* stream);
+
+/*
+ * bs_estimate_noalloc — bs_estimate for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same launches and the same results, with the
+ * workspace replaced by a fixed scratch array of BS_NOALLOC_SCRATCH_BYTES
+ * that the library holds in device memory, one copy per GPU, from the first
+ * call on that GPU until the process ends. The call allocates nothing.
+ *   Scratch use: the FP64 T table, align256(8 (N + 1)) bytes (at most
+ *   513 KB), plus align256(4 nA) if popA is NULL and align256(4 nB) if popB
+ *   is NULL. A call needing more returns BS_ERR_SCRATCH before any launch
+ *   (pass popA / popB, e.g. the popcounts bs_sketch writes, to lift the row
+ *   limit: then any nA, nB are accepted).
+ *   Every call on a GPU uses that GPU's one array, and each call writes all
+ *   the scratch it reads, so consecutive calls need no clearing; calls that
+ *   overlap in time on one GPU (different streams or host threads) race on
+ *   the array and give undefined results.
+ * Arguments and the other statuses as bs_estimate, without the workspace.
+ */
+#define BS_NOALLOC_SCRATCH_BYTES (4u << 20)
+bs_status bs_estimate_noalloc(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                              const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
+                              double* js, double* cos, void* stream);
 
 /*
  * bs_topk — for every query row Q_p, the k corpus rows C_q with the best

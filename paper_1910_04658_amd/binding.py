@@ -19,9 +19,10 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libbinsketch.so")
 
-BS_OK, BS_ERR_NULL, BS_ERR_ARG, BS_ERR_WORKSPACE, BS_ERR_HIP, BS_ERR_DEVICE = range(6)
+BS_OK, BS_ERR_NULL, BS_ERR_ARG, BS_ERR_WORKSPACE, BS_ERR_HIP, BS_ERR_DEVICE, BS_ERR_SCRATCH = range(7)
 BS_IP, BS_HAMMING, BS_JACCARD, BS_COSINE = range(4)
 FLAG_INDPTR, FLAG_INDEX, FLAG_MAP = 1, 2, 4
+NOALLOC_SCRATCH_BYTES = 4 << 20  # BS_NOALLOC_SCRATCH_BYTES
 MEASURES = {"ip": BS_IP, "ham": BS_HAMMING, "hamming": BS_HAMMING, "js": BS_JACCARD,
             "jaccard": BS_JACCARD, "cos": BS_COSINE, "cosine": BS_COSINE}
 
@@ -88,6 +89,8 @@ def load():
             L.bs_estimate_workspace_size.restype = sz
             L.bs_estimate.argtypes = [p, p, i64, p, p, i64, i32, p, p, p, p, p, sz, p]
             L.bs_estimate.restype = ctypes.c_int
+            L.bs_estimate_noalloc.argtypes = [p, p, i64, p, p, i64, i32, p, p, p, p, p]
+            L.bs_estimate_noalloc.restype = ctypes.c_int
             L.bs_topk_workspace_size.argtypes = [i64, i64, i32, i32]
             L.bs_topk_workspace_size.restype = sz
             L.bs_topk_sample_size.argtypes = [i64]
@@ -333,6 +336,36 @@ def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "j
                        _ptr(outs.get("js")), _ptr(outs.get("cos")), _ptr(workspace), workspace.numel(),
                        _stream())
     _check(st, "bs_estimate")
+    return outs
+
+
+def estimate_noalloc(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "js", "cos"),
+                     popA: torch.Tensor | None = None, popB: torch.Tensor | None = None, outs=None):
+    """bs_estimate_noalloc: bs_estimate on the library's fixed scratch (no
+    workspace). `outs` (dict measure -> float64[nA][nB]) may be given, e.g.
+    preallocated outside a graph capture; missing ones are allocated here."""
+    W = words(N)
+    _need(A, "A", torch.int64, 2)
+    _need(B, "B", torch.int64, 2)
+    popA = _opt_pop(popA, A.shape[0], "popA")
+    popB = _opt_pop(popB, B.shape[0], "popB")
+    if A.shape[1] != W or B.shape[1] != W:
+        raise ValueError("sketch rows must hold N/64 words")
+    nA, nB = A.shape[0], B.shape[0]
+    outs = dict(outs or {})
+    for m in measures:
+        key = {"ip": "ip", "ham": "ham", "hamming": "ham", "js": "js", "jaccard": "js",
+               "cos": "cos", "cosine": "cos"}[m]
+        if key not in outs:
+            outs[key] = torch.empty((nA, nB), dtype=torch.float64, device=A.device)
+    for t in outs.values():
+        _need(t, "output", torch.float64, 2)
+        if tuple(t.shape) != (nA, nB):
+            raise ValueError("outputs must be [nA][nB]")
+    L = load()
+    st = L.bs_estimate_noalloc(_ptr(A), _ptr(popA), nA, _ptr(B), _ptr(popB), nB, int(N), _ptr(outs.get("ip")),
+                               _ptr(outs.get("ham")), _ptr(outs.get("js")), _ptr(outs.get("cos")), _stream())
+    _check(st, "bs_estimate_noalloc")
     return outs
 
 

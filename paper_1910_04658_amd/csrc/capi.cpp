@@ -38,7 +38,7 @@ hipEvent_t take_event() {
 
 ScopedTiming::ScopedTiming(const char* name, hipStream_t s) : name_(name), s_(s) {
   std::lock_guard<std::mutex> lock(g_tmu);
-  if (!g_timing) return;
+  if (!g_timing || !name_) return;  // a null name: never timed (creates no events)
   // launches recorded into a graph are timed only as a whole, by the caller
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
@@ -111,6 +111,8 @@ extern "C" const char* bs_status_string(int status) {
       return "the HIP runtime rejected a launch";
     case BS_ERR_DEVICE:
       return "the current device is not a gfx950";
+    case BS_ERR_SCRATCH:
+      return "the call needs more than the fixed no-allocation scratch (BS_NOALLOC_SCRATCH_BYTES)";
     default:
       return "unknown status";
   }

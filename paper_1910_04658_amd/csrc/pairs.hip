@@ -15,6 +15,8 @@
 // the saturation clamp), and x_u = x_a + x_b - x_ab = |a_s OR b_s|,
 //   s = T(x_a) + T(x_b),  ip = s - T(x_u),  ham = s - 2 ip,
 //   js = ip / (ip + ham),  cos = ip / sqrt(T(x_a) T(x_b)).
+#include <mutex>
+
 #include "bs_common.h"
 
 namespace bs {
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
 }
 
 template <bool EST>
-bs_status launch_dense(DenseArgs a, hipStream_t s) {
+bs_status launch_dense(DenseArgs a, hipStream_t s, bool timed = true) {
   const int W32 = a.W32;
   // Largest power of two <= 64 that divides W32 (W32 is even).
   int WC = 64;
@@ -185,7 +187,7 @@ bs_status launch_dense(DenseArgs a, hipStream_t s) {
   if (bblocks > INT32_MAX || ablocks > 65535) return BS_ERR_ARG;
   dim3 grid((unsigned)bblocks, (unsigned)ablocks);
   dim3 block(kPairThreads);
-  ScopedTiming timing(EST ? "pair_estimate" : "pair_and_popcount", s);
+  ScopedTiming timing(timed ? (EST ? "pair_estimate" : "pair_and_popcount") : nullptr, s);
 #define BS_DENSE_CASE(wc, ta)                                                          \
   case wc:                                                                             \
     hipLaunchKernelGGL((pair_dense_kernel<wc, ta, EST>), grid, block, 0, s, a); \
@@ -226,39 +228,62 @@ extern "C" bs_status bs_and_popcount(const uint64_t* A, int64_t nA, const uint64
   return launch_dense<false>(a, as_stream(stream));
 }
 
-extern "C" size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N) {
-  using namespace bs;
-  if (!valid_width(N) || nA < 0 || nB < 0) return 0;
-  return align256((size_t)(N + 1) * sizeof(double)) + align256((size_t)nA * 4) +
-         align256((size_t)nB * 4);
+// Fixed scratch of bs_estimate_noalloc: the T table and, when the caller
+// passes none, the row popcounts. One copy per GPU, held until the process
+// ends; host code reaches it only through the address hipGetSymbolAddress
+// returns for the current device.
+static __device__ __align__(256) unsigned char scratch[BS_NOALLOC_SCRATCH_BYTES];
+
+namespace bs {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// Address of the current device's copy of `scratch`, looked up on the first
+// call on that device (with it current) and kept.
+bs_status noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BS_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return BS_ERR_HIP;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return BS_OK;
 }
 
-extern "C" bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
-                                 const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
-                                 double* js, double* cos, void* workspace, size_t workspace_bytes,
-                                 void* stream) {
-  using namespace bs;
+// Bytes of scratch bs_estimate needs: the FP64 T table, then the row
+// popcounts that the caller did not pass.
+// Saturates at SIZE_MAX (row counts are only bounded by nA * nB < 2^62).
+size_t estimate_scratch_bytes(int64_t nA, int64_t nB, int32_t N, bool needA, bool needB) {
+  const int64_t cap = INT64_C(1) << 40;
+  if ((needA && nA > cap) || (needB && nB > cap)) return SIZE_MAX;
+  return align256((size_t)(N + 1) * sizeof(double)) + (needA ? align256((size_t)nA * 4) : 0) +
+         (needB ? align256((size_t)nB * 4) : 0);
+}
+
+bs_status estimate_check(const uint64_t* A, int64_t nA, const uint64_t* B, int64_t nB, int32_t N, const double* ip,
+                         const double* ham, const double* js, const double* cos) {
   if (nA < 0 || nB < 0 || !valid_width(N)) return BS_ERR_ARG;
   if ((!A && nA > 0) || (!B && nB > 0)) return BS_ERR_NULL;
   if (!ip && !ham && !js && !cos) return BS_ERR_NULL;
   if (nA > 0 && nB > (INT64_C(1) << 62) / nA) return BS_ERR_ARG;
-  const size_t need = bs_estimate_workspace_size(nA, nB, N);
-  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
-    return BS_ERR_WORKSPACE;
-  bs_status st = check_device();
-  if (st != BS_OK) return st;
-  if (nA == 0 || nB == 0) return BS_OK;
-  char* ws = static_cast<char*>(workspace);
-  double* t64 = reinterpret_cast<double*>(ws);
-  ws += align256((size_t)(N + 1) * sizeof(double));
-  int32_t* wpopA = reinterpret_cast<int32_t*>(ws);
-  ws += align256((size_t)nA * 4);
-  int32_t* wpopB = reinterpret_cast<int32_t*>(ws);
-  hipStream_t s = as_stream(stream);
+  return BS_OK;
+}
+
+// The estimate's launches: the FP64 T table into t64, the row popcounts the
+// caller did not pass into wpopA / wpopB, then the dense estimate kernel.
+bs_status estimate_run(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B, const int32_t* popB,
+                       int64_t nB, int32_t N, double* ip, double* ham, double* js, double* cos, double* t64,
+                       int32_t* wpopA, int32_t* wpopB, hipStream_t s, bool timed) {
   launch_lut(N, t64, nullptr, s);
   if (!popA) launch_row_popcount(A, nA, N, wpopA, s);
   if (!popB) launch_row_popcount(B, nB, N, wpopB, s);
-  st = launch_status();
+  bs_status st = launch_status();
   if (st != BS_OK) return st;
   DenseArgs a = {};
   a.A = reinterpret_cast<const uint32_t*>(A);
@@ -273,7 +298,61 @@ extern "C" bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t
   a.nA = nA;
   a.nB = nB;
   a.W32 = N / 32;
-  return launch_dense<true>(a, s);
+  return launch_dense<true>(a, s, timed);
+}
+
+}  // namespace
+}  // namespace bs
+
+extern "C" size_t bs_estimate_workspace_size(int64_t nA, int64_t nB, int32_t N) {
+  using namespace bs;
+  if (!valid_width(N) || nA < 0 || nB < 0) return 0;
+  return align256((size_t)(N + 1) * sizeof(double)) + align256((size_t)nA * 4) +
+         align256((size_t)nB * 4);
+}
+
+extern "C" bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                                 const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
+                                 double* js, double* cos, void* workspace, size_t workspace_bytes,
+                                 void* stream) {
+  using namespace bs;
+  bs_status st = estimate_check(A, nA, B, nB, N, ip, ham, js, cos);
+  if (st != BS_OK) return st;
+  const size_t need = bs_estimate_workspace_size(nA, nB, N);
+  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return BS_ERR_WORKSPACE;
+  st = check_device();
+  if (st != BS_OK) return st;
+  if (nA == 0 || nB == 0) return BS_OK;
+  char* ws = static_cast<char*>(workspace);
+  double* t64 = reinterpret_cast<double*>(ws);
+  int32_t* wpopA = reinterpret_cast<int32_t*>(ws + align256((size_t)(N + 1) * sizeof(double)));
+  int32_t* wpopB = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(wpopA) + align256((size_t)nA * 4));
+  return estimate_run(A, popA, nA, B, popB, nB, N, ip, ham, js, cos, t64, wpopA, wpopB, as_stream(stream), true);
+}
+
+extern "C" bs_status bs_estimate_noalloc(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                                         const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
+                                         double* js, double* cos, void* stream) {
+  using namespace bs;
+  bs_status st = estimate_check(A, nA, B, nB, N, ip, ham, js, cos);
+  if (st != BS_OK) return st;
+  if (estimate_scratch_bytes(nA, nB, N, !popA, !popB) > (size_t)BS_NOALLOC_SCRATCH_BYTES) return BS_ERR_SCRATCH;
+  st = check_device();
+  if (st != BS_OK) return st;
+  if (nA == 0 || nB == 0) return BS_OK;
+  void* base = nullptr;
+  st = noalloc_scratch(&base);
+  if (st != BS_OK) return st;
+  // scratch layout as estimate_scratch_bytes: T, then the missing popcounts;
+  // every word is written before it is read, so nothing is cleared
+  char* ws = static_cast<char*>(base);
+  double* t64 = reinterpret_cast<double*>(ws);
+  ws += align256((size_t)(N + 1) * sizeof(double));
+  int32_t* wpopA = popA ? nullptr : reinterpret_cast<int32_t*>(ws);
+  if (!popA) ws += align256((size_t)nA * 4);
+  int32_t* wpopB = popB ? nullptr : reinterpret_cast<int32_t*>(ws);
+  return estimate_run(A, popA, nA, B, popB, nB, N, ip, ham, js, cos, t64, wpopA, wpopB, as_stream(stream), false);
 }
 
 extern "C" bs_status bs_pair_popcount(const uint64_t* A, int64_t nA, const int32_t* ia, const uint64_t* B,

@@ -82,6 +82,24 @@ def test_pairs_reject_bad_arguments(lib):
     assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, P(0x1001), need, None) == 3
 
 
+def test_estimate_noalloc_rejects_on_the_host(lib):
+    """bs_estimate_noalloc checks its arguments as bs_estimate does, and a call
+    whose row popcounts would not fit the fixed scratch (after the T table)
+    returns BS_ERR_SCRATCH before any launch. At N = 64 the table takes 768
+    bytes, so 1,048,384 computed popcounts fill the 4 MiB exactly and one
+    more row does not fit."""
+    f = lib.bs_estimate_noalloc
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, None, None, None, None, None) == 1    # no output
+    assert f(None, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, None) == 1
+    assert f(FAKE, None, 1, FAKE, None, 1, 65, FAKE, None, None, None, None) == 2    # bad width
+    assert f(FAKE, None, -1, FAKE, None, 1, 64, FAKE, None, None, None, None) == 2
+    assert f(FAKE, None, 1_048_385, FAKE, FAKE, 1, 64, FAKE, None, None, None, None) == 6
+    assert f(FAKE, FAKE, 1, FAKE, None, 1_048_385, 64, FAKE, None, None, None, None) == 6
+    assert f(FAKE, None, 1_000_000, FAKE, None, 1, 65536, FAKE, None, None, None, None) == 6
+    assert f(FAKE, None, 2 ** 50, FAKE, FAKE, 1, 64, FAKE, None, None, None, None) == 6
+    assert lib.bs_status_string(6).startswith(b"the call needs more than the fixed no-allocation scratch")
+
+
 def test_topk_rejects_bad_arguments(lib):
     t = lib.bs_topk
     need = lib.bs_topk_workspace_size(10, 100, 256, 5)
