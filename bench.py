@@ -254,6 +254,63 @@ def jaccard_mse(step, corpus, queries):
             "top100_pairs": mse_top, "top100_mean_estimate": mean_js_top}
 
 
+def dense_eval(dev, reps=50):
+    """All-pairs estimates of the small corpus (1,000 vectors, d = 10,000,
+    Zipf(1.1) lengths in [5, 500], N = 1024): sketch, then all 1,000 x 1,000
+    IP / Hamming / Jaccard / cosine estimates in FP64 (Algorithms 1-4), 32 MB
+    of output. The estimate kernel is bound by its HBM writes."""
+    import torch
+
+    import datagen
+    from paper_1910_04658_amd import binding as bs
+    N = 1024
+    c = datagen.small_corpus()
+    pi = datagen.random_map(c.d, N, datagen.SEED_PI)
+    to = lambda a: torch.from_numpy(a).to(dev)  # noqa: E731
+    indptr, indices, pi_d = to(c.indptr), to(c.indices), to(pi)
+    n = c.n
+    W = torch.empty((n, N // 64), dtype=torch.int64, device=dev)
+    pop = torch.empty(n, dtype=torch.int32, device=dev)
+    outs = {k: torch.empty((n, n), dtype=torch.float64, device=dev) for k in ("ip", "ham", "js", "cos")}
+    sws = bs._workspace(bs.sketch_workspace_size(c.d, N), dev)
+    L = bs.load()
+    ews = bs._workspace(L.bs_estimate_workspace_size(n, n, N), dev)
+
+    def step():
+        bs.sketch(indptr, indices, pi_d, N, out=W, popcounts=pop, workspace=sws)
+        st = L.bs_estimate(bs._ptr(W), bs._ptr(pop), n, bs._ptr(W), bs._ptr(pop), n, N, bs._ptr(outs["ip"]),
+                           bs._ptr(outs["ham"]), bs._ptr(outs["js"]), bs._ptr(outs["cos"]), bs._ptr(ews),
+                           ews.numel(), bs._stream())
+        bs._check(st, "bs_estimate")
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    bs.timing_collect()
+    bs.timing_reset()
+    bs.timing_enable(True)
+    for _ in range(10):
+        step()
+    torch.cuda.synchronize()
+    bs.timing_enable(False)
+    bs.timing_collect()
+    est_ms, cnt = bs.timing_get("pair_estimate")
+    est_ms /= max(cnt, 1)
+    # algorithmic bytes of the estimate launch: 4 planes of n*n doubles
+    # written, both sketch matrices and popcounts read once
+    by = 4 * n * n * 8 + 2 * n * (N // 8) + 2 * n * 4
+    ach = by / (est_ms * 1e-3) / 1e9
+    return {"workload": "all-pairs estimates, 1,000 x 1,000 (diagonal included), N = 1024, FP64, 4 measures",
+            "rows": n, "nnz": int(c.nnz), "ms_per_step": ms, "pair_estimates_per_s": n * n / (ms * 1e-3),
+            "estimate_kernel_ms": est_ms,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": ach / PEAK_HBM_GBS, "bytes_per_launch": by, "kernel": "pair_estimate"}}
+
+
 def ranking_eval(dev, max_queries=500, widths=(256, 1024, 4096)):
     """Threshold retrieval (Section 4.2, Experiment 2) on synthetic rows with
     planted near-duplicates, split 90/10 into corpus and queries: for every
@@ -489,6 +546,7 @@ def main():
     ap.add_argument("--no-ranking", action="store_true", help="skip the threshold-retrieval evaluation")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving run")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
+    ap.add_argument("--no-dense", action="store_true", help="skip the small-corpus all-pairs estimate run")
     ap.add_argument("--graph", action="store_true", help="time replays of the step recorded into a HIP graph")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
@@ -585,12 +643,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp4",
+        # scores are FP32; the pair counts behind them are exact integers (0/1
+        # FP4 matrix-core operands with FP32 accumulators, or VALU popcounts)
+        "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "BinSketch sketch + top-100 Jaccard query-vs-corpus", "N": args.N,
                    "n_corpus": nC, "n_queries": nQ, "d": corpus.d, "k": k,
                    "row_length": "round(lognormal), mean 230, sd 150",
-                   "feature_popularity": "Zipf(1.1)", "score_dtype": "f32", "pair_counts": "exact: 0/1 FP4 operands, FP32 accumulators", "parallelism": "single GPU"},
+                   "feature_popularity": "Zipf(1.1)", "score_dtype": "f32",
+                   "pair_counts": "exact integers: 0/1 FP4 matrix-core operands with FP32 accumulators "
+                                  "(N a multiple of 512), else VALU AND + popcount", "parallelism": "single GPU"},
         "sketched_vectors_per_s": sketch_rate(kt),
         "pair_estimates_per_s": value,
         "kernels_ms": {n: v["avg_ms"] for n, v in kt.items()},
@@ -608,6 +670,10 @@ def main():
                                  "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
     if not args.no_mse:
         out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.no_dense:
+        log("all-pairs estimates of the small corpus ...")
+        out["dense_small_corpus"] = dense_eval(dev)
+        log("dense: %s" % out["dense_small_corpus"])
     if not args.no_batch:
         log("batched problems ...")
         out["batching"] = batch_eval(dev)

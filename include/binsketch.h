@@ -53,6 +53,8 @@ typedef enum {
 
 typedef enum { BS_IP = 0, BS_HAMMING = 1, BS_JACCARD = 2, BS_COSINE = 3 } bs_measure;
 
+typedef enum { BS_F64 = 0, BS_F32 = 1 } bs_dtype;
+
 /* Bits that bs_sketch ORs into *err_flag. */
 #define BS_FLAG_INDPTR 1 /* indptr[0] != 0, not non-decreasing, or beyond nnz */
 #define BS_FLAG_INDEX 2  /* a CSR index outside [0, d) */
@@ -176,6 +178,23 @@ bs_status bs_estimate(const uint64_t* A, const int32_t* popA, int64_t nA, const 
                       const int32_t* popB, int64_t nB, int32_t N, double* ip, double* ham,
                       double* js, double* cos, void* workspace, size_t workspace_bytes,
                       void* stream);
+
+/*
+ * bs_estimate_scores — the all-pairs estimates of ONE measure (Algorithms
+ * 1-4, chosen by `measure`, a bs_measure) as a dense row-major [nA][nB]
+ * matrix `scores` of score_dtype:
+ *   BS_F64  double: exactly the plane bs_estimate writes for that measure;
+ *   BS_F32  float: the score bs_topk ranks by, i.e. the same expressions
+ *           evaluated in IEEE float from T rounded once to float
+ *           (s = T(x_a) + T(x_b), ip = s - T(x_u), ham = s - 2 ip, ...),
+ *           so a row's k best entries are bs_topk's result for that query.
+ * popA, popB, workspace (bs_estimate_workspace_size bytes, 256-byte aligned)
+ * and the statuses as bs_estimate; BS_ERR_ARG also for a measure or
+ * score_dtype out of range, BS_ERR_NULL for a NULL scores.
+ */
+bs_status bs_estimate_scores(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                             const int32_t* popB, int64_t nB, int32_t N, int32_t measure, void* scores,
+                             int32_t score_dtype, void* workspace, size_t workspace_bytes, void* stream);
 
 /*
  * bs_estimate_noalloc — bs_estimate for callers that cannot allocate device
@@ -383,8 +402,8 @@ int bs_timing_get(const char* name, double* total_ms, int64_t* count);
  * and selects at most `lds_keys` candidates in LDS (larger sets are
  * compacted and selected in place in the workspace). Negative values
  * restore the automatic sizes. Lets tests drive the overflow and in-place
- * paths, which must return the same result. Process-wide; not thread-safe.
- * Returns 0.
+ * paths, which must return the same result. Applies to the calling host
+ * thread only (each thread has its own setting). Returns 0.
  */
 int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys);
 
@@ -395,7 +414,7 @@ int bs_debug_set_topk_limits(int64_t slab_capacity, int64_t lds_keys);
  * select's check that at least k candidates score >= tau and are ranked by
  * the whole-corpus fallback). A rank below 1 restores the automatic choice.
  * Lets tests drive the fallback on a failed check, which must return the same
- * result. Process-wide; not thread-safe. Returns 0.
+ * result. Applies to the calling host thread only. Returns 0.
  */
 int bs_debug_set_topk_tau_rank(int64_t rank);
 
@@ -406,7 +425,7 @@ int bs_debug_set_topk_tau_rank(int64_t rank);
  * queries); any other value restores the automatic choice. The two scans
  * produce the same candidates; lets tests cover both. bs_topk_workspace_size
  * follows the same choice, so size the workspace after setting it.
- * Process-wide; not thread-safe. Returns 0.
+ * Applies to the calling host thread only. Returns 0.
  */
 int bs_debug_set_topk_mma(int32_t on);
 

@@ -89,6 +89,8 @@ def load():
             L.bs_estimate_workspace_size.restype = sz
             L.bs_estimate.argtypes = [p, p, i64, p, p, i64, i32, p, p, p, p, p, sz, p]
             L.bs_estimate.restype = ctypes.c_int
+            L.bs_estimate_scores.argtypes = [p, p, i64, p, p, i64, i32, i32, p, i32, p, sz, p]
+            L.bs_estimate_scores.restype = ctypes.c_int
             L.bs_estimate_noalloc.argtypes = [p, p, i64, p, p, i64, i32, p, p, p, p, p]
             L.bs_estimate_noalloc.restype = ctypes.c_int
             L.bs_topk_workspace_size.argtypes = [i64, i64, i32, i32]
@@ -192,9 +194,9 @@ def sketch_workspace_size(d: int, N: int) -> int:
 def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int,
            out: torch.Tensor | None = None, popcounts: bool | torch.Tensor = True,
            err_flag: torch.Tensor | None = None, workspace: torch.Tensor | None | bool = True):
-    """bs_sketch. workspace: a device buffer of sketch_workspace_size(d, N)
-    bytes, True to allocate one, or None/False for the global-gather path."""
-    """bs_sketch: (sketches int64[n][N/64], popcounts int32[n] or None)."""
+    """bs_sketch: (sketches int64[n][N/64], popcounts int32[n] or None).
+    workspace: a device buffer of sketch_workspace_size(d, N) bytes, True to
+    allocate one, or None/False for the global-gather path."""
     _need(indptr, "indptr", torch.int32, 1)
     _need(indices, "indices", torch.int32, 1)
     _need(pi, "pi", torch.int32, 1)
@@ -301,6 +303,10 @@ def and_popcount(A: torch.Tensor, B: torch.Tensor, N: int, out: torch.Tensor | N
     return out
 
 
+def _measure(measure) -> int:
+    return MEASURES[measure] if isinstance(measure, str) else int(measure)
+
+
 def _opt_pop(t, n, name):
     if t is None:
         return None
@@ -337,6 +343,36 @@ def estimate(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "j
                        _stream())
     _check(st, "bs_estimate")
     return outs
+
+
+def estimate_scores(A: torch.Tensor, B: torch.Tensor, N: int, measure, dtype=torch.float32,
+                    workspace: torch.Tensor | None = None, popA: torch.Tensor | None = None,
+                    popB: torch.Tensor | None = None, out: torch.Tensor | None = None):
+    """bs_estimate_scores: one measure's [nA][nB] scores, float32 (the values
+    bs_topk ranks by) or float64 (bs_estimate's plane)."""
+    W = words(N)
+    _need(A, "A", torch.int64, 2)
+    _need(B, "B", torch.int64, 2)
+    popA = _opt_pop(popA, A.shape[0], "popA")
+    popB = _opt_pop(popB, B.shape[0], "popB")
+    if A.shape[1] != W or B.shape[1] != W:
+        raise ValueError("sketch rows must hold N/64 words")
+    if dtype not in (torch.float32, torch.float64):
+        raise TypeError("dtype must be float32 or float64")
+    nA, nB = A.shape[0], B.shape[0]
+    if out is None:
+        out = torch.empty((nA, nB), dtype=dtype, device=A.device)
+    _need(out, "out", dtype, 2)
+    if tuple(out.shape) != (nA, nB):
+        raise ValueError("out must be [nA][nB]")
+    L = load()
+    if workspace is None:
+        workspace = _workspace(L.bs_estimate_workspace_size(nA, nB, int(N)), A.device)
+    st = L.bs_estimate_scores(_ptr(A), _ptr(popA), nA, _ptr(B), _ptr(popB), nB, int(N), _measure(measure),
+                              _ptr(out), 1 if dtype == torch.float32 else 0, _ptr(workspace), workspace.numel(),
+                              _stream())
+    _check(st, "bs_estimate_scores")
+    return out
 
 
 def estimate_noalloc(A: torch.Tensor, B: torch.Tensor, N: int, measures=("ip", "ham", "js", "cos"),

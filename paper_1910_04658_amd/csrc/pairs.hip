@@ -89,8 +89,10 @@ struct DenseArgs {
   const uint32_t* __restrict__ B;  // [nB][W32]
   const int32_t* __restrict__ popA;
   const int32_t* __restrict__ popB;
-  const double* __restrict__ t64;  // T(0..N)
+  const double* __restrict__ t64;  // T(0..N) (mode 1)
+  const float* __restrict__ t32;   // T(0..N) rounded to float (mode 2)
   int32_t* __restrict__ xab_out;   // [nA][nB] (mode 0)
+  float* __restrict__ f32;         // [nA][nB] (mode 2): one measure, FP32
   double* __restrict__ ip;         // [nA][nB] (mode 1), each may be null
   double* __restrict__ ham;
   double* __restrict__ js;
@@ -101,8 +103,11 @@ struct DenseArgs {
 };
 
 // WC: 32-bit words of B held in VGPRs per chunk; TA: A rows per tile.
-template <int WC, int TA, bool EST>
+// MODE 0: counts x_ab; 1: FP64 estimates (any of the four planes); 2: the
+// FP32 score of measure M (the value bs_topk ranks by).
+template <int WC, int TA, int MODE, int M>
 __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
+  constexpr bool EST = MODE != 0;
   const int64_t b = (int64_t)blockIdx.x * kPairThreads + threadIdx.x;
   const bool b_ok = b < a.nB;
   const int64_t bb = b_ok ? b : a.nB - 1;
@@ -114,11 +119,11 @@ __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
   const uint32_t* brow = a.B + (size_t)bb * W32;
 
   double Tb = 0.0;
+  float Tb32 = 0.0f;
   int32_t xb = 0;
-  if (EST) {
-    xb = a.popB[bb];
-    Tb = a.t64[xb];
-  }
+  if (EST) xb = a.popB[bb];
+  if (MODE == 1) Tb = a.t64[xb];
+  if (MODE == 2) Tb32 = a.t32[xb];
 
   uint32_t bw[WC];
   if (nchunks == 1) {
@@ -147,8 +152,12 @@ __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
       const int64_t ar = a0 + t;
       if (ar >= a_end || !b_ok) continue;
       const size_t o = (size_t)ar * a.nB + b;
-      if (!EST) {
+      if (MODE == 0) {
         __builtin_nontemporal_store((int32_t)acc[t], a.xab_out + o);
+      } else if (MODE == 2) {
+        const int32_t xa = as_const(a.popA)[ar];
+        const float sc = score_f32<M>(a.t32[xa], Tb32, a.t32[xa + xb - (int32_t)acc[t]]);
+        __builtin_nontemporal_store(sc, a.f32 + o);
       } else {
         const int32_t xa = as_const(a.popA)[ar];
         const double Ta = a.t64[xa];
@@ -171,7 +180,7 @@ __global__ __launch_bounds__(kPairThreads) void pair_dense_kernel(DenseArgs a) {
   }
 }
 
-template <bool EST>
+template <int MODE, int M = 0>
 bs_status launch_dense(DenseArgs a, hipStream_t s, bool timed = true) {
   const int W32 = a.W32;
   // Largest power of two <= 64 that divides W32 (W32 is even).
@@ -187,10 +196,10 @@ bs_status launch_dense(DenseArgs a, hipStream_t s, bool timed = true) {
   if (bblocks > INT32_MAX || ablocks > 65535) return BS_ERR_ARG;
   dim3 grid((unsigned)bblocks, (unsigned)ablocks);
   dim3 block(kPairThreads);
-  ScopedTiming timing(timed ? (EST ? "pair_estimate" : "pair_and_popcount") : nullptr, s);
+  ScopedTiming timing(timed ? (MODE != 0 ? "pair_estimate" : "pair_and_popcount") : nullptr, s);
 #define BS_DENSE_CASE(wc, ta)                                                          \
   case wc:                                                                             \
-    hipLaunchKernelGGL((pair_dense_kernel<wc, ta, EST>), grid, block, 0, s, a); \
+    hipLaunchKernelGGL((pair_dense_kernel<wc, ta, MODE, M>), grid, block, 0, s, a); \
     break;
   switch (WC) {
     BS_DENSE_CASE(2, 4)
@@ -225,7 +234,7 @@ extern "C" bs_status bs_and_popcount(const uint64_t* A, int64_t nA, const uint64
   a.nA = nA;
   a.nB = nB;
   a.W32 = N / 32;
-  return launch_dense<false>(a, as_stream(stream));
+  return launch_dense<0>(a, as_stream(stream));
 }
 
 // Fixed scratch of bs_estimate_noalloc: the T table and, when the caller
@@ -298,7 +307,7 @@ bs_status estimate_run(const uint64_t* A, const int32_t* popA, int64_t nA, const
   a.nA = nA;
   a.nB = nB;
   a.W32 = N / 32;
-  return launch_dense<true>(a, s, timed);
+  return launch_dense<1>(a, s, timed);
 }
 
 }  // namespace
@@ -353,6 +362,57 @@ extern "C" bs_status bs_estimate_noalloc(const uint64_t* A, const int32_t* popA,
   if (!popA) ws += align256((size_t)nA * 4);
   int32_t* wpopB = popB ? nullptr : reinterpret_cast<int32_t*>(ws);
   return estimate_run(A, popA, nA, B, popB, nB, N, ip, ham, js, cos, t64, wpopA, wpopB, as_stream(stream), false);
+}
+
+extern "C" bs_status bs_estimate_scores(const uint64_t* A, const int32_t* popA, int64_t nA, const uint64_t* B,
+                                        const int32_t* popB, int64_t nB, int32_t N, int32_t measure, void* scores,
+                                        int32_t score_dtype, void* workspace, size_t workspace_bytes, void* stream) {
+  using namespace bs;
+  if (measure < BS_IP || measure > BS_COSINE || (score_dtype != BS_F64 && score_dtype != BS_F32)) return BS_ERR_ARG;
+  if (score_dtype == BS_F64) {
+    double* out = static_cast<double*>(scores);
+    return bs_estimate(A, popA, nA, B, popB, nB, N, measure == BS_IP ? out : nullptr,
+                       measure == BS_HAMMING ? out : nullptr, measure == BS_JACCARD ? out : nullptr,
+                       measure == BS_COSINE ? out : nullptr, workspace, workspace_bytes, stream);
+  }
+  float* out = static_cast<float*>(scores);
+  if (nA < 0 || nB < 0 || !valid_width(N)) return BS_ERR_ARG;
+  if ((!A && nA > 0) || (!B && nB > 0) || !out) return BS_ERR_NULL;
+  if (nA > 0 && nB > (INT64_C(1) << 62) / nA) return BS_ERR_ARG;
+  bs_status st = BS_OK;
+  const size_t need = bs_estimate_workspace_size(nA, nB, N);
+  if (!workspace || workspace_bytes < need || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return BS_ERR_WORKSPACE;
+  st = check_device();
+  if (st != BS_OK) return st;
+  if (nA == 0 || nB == 0) return BS_OK;
+  // the workspace layout of bs_estimate, with the FP32 table in the FP64 table's place
+  char* ws = static_cast<char*>(workspace);
+  float* t32 = reinterpret_cast<float*>(ws);
+  int32_t* wpopA = reinterpret_cast<int32_t*>(ws + align256((size_t)(N + 1) * sizeof(double)));
+  int32_t* wpopB = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(wpopA) + align256((size_t)nA * 4));
+  hipStream_t s = as_stream(stream);
+  launch_lut(N, nullptr, t32, s);
+  if (!popA) launch_row_popcount(A, nA, N, wpopA, s);
+  if (!popB) launch_row_popcount(B, nB, N, wpopB, s);
+  st = launch_status();
+  if (st != BS_OK) return st;
+  DenseArgs a = {};
+  a.A = reinterpret_cast<const uint32_t*>(A);
+  a.B = reinterpret_cast<const uint32_t*>(B);
+  a.popA = popA ? popA : wpopA;
+  a.popB = popB ? popB : wpopB;
+  a.t32 = t32;
+  a.f32 = out;
+  a.nA = nA;
+  a.nB = nB;
+  a.W32 = N / 32;
+  switch (measure) {
+    case BS_IP: return launch_dense<2, BS_IP>(a, s);
+    case BS_HAMMING: return launch_dense<2, BS_HAMMING>(a, s);
+    case BS_JACCARD: return launch_dense<2, BS_JACCARD>(a, s);
+    default: return launch_dense<2, BS_COSINE>(a, s);
+  }
 }
 
 extern "C" bs_status bs_pair_popcount(const uint64_t* A, int64_t nA, const int32_t* ia, const uint64_t* B,

@@ -82,6 +82,19 @@ def test_pairs_reject_bad_arguments(lib):
     assert lib.bs_estimate(FAKE, None, 1, FAKE, None, 1, 64, FAKE, None, None, None, P(0x1001), need, None) == 3
 
 
+def test_estimate_scores_rejects_bad_arguments(lib):
+    f = lib.bs_estimate_scores
+    need = lib.bs_estimate_workspace_size(1, 1, 64)
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 4, FAKE, 1, FAKE, need, None) == 2   # measure
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, -1, FAKE, 0, FAKE, need, None) == 2
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 2, FAKE, 2, FAKE, need, None) == 2   # dtype
+    assert f(FAKE, None, 1, FAKE, None, 1, 96, 2, FAKE, 1, FAKE, need, None) == 2   # width
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 2, None, 1, FAKE, need, None) == 1   # no output
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 2, None, 0, FAKE, need, None) == 1
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 2, FAKE, 1, None, need, None) == 3   # workspace
+    assert f(FAKE, None, 1, FAKE, None, 1, 64, 2, FAKE, 0, FAKE, need - 1, None) == 3
+
+
 def test_estimate_noalloc_rejects_on_the_host(lib):
     """bs_estimate_noalloc checks its arguments as bs_estimate does, and a call
     whose row popcounts would not fit the fixed scratch (after the T table)

@@ -83,3 +83,33 @@ def test_one_by_one_and_empty(dev):
     e = bs.and_popcount(w[:0].contiguous(), w, 128)
     torch.cuda.synchronize()
     assert e.shape == (0, 3)
+
+
+@pytest.mark.parametrize("N", [64, 1024, 4096])
+def test_measure_scores_fp32_and_fp64(N, dev):
+    """bs_estimate_scores: the FP32 matrix of each measure is bit-equal to the
+    oracle's FP32 score of every pair (the value bs_topk ranks by), empty and
+    full rows included; the FP64 matrix is bs_estimate's plane. 150 x 211
+    pairs, popcounts passed for A and computed for B."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    c = datagen.saturation_rows(211, N, 61 + N, p_empty=0.05, p_full=0.05, p_near=0.05)
+    pi = datagen.identity_map(N)
+    w, pop = bs.sketch(to_dev(c.indptr, dev), to_dev(c.indices, dev), to_dev(pi, dev), N)
+    S = oracle.sketch_sets(c.indptr, c.indices, N, pi, N)
+    a = np.arange(0, 211, 7).tolist() + list(range(60, 180))
+    a = sorted(set(a))[:150]
+    A = w[a].contiguous()
+    X = oracle.intersections(sets_rows(S, a), S)
+    xa, xb = S.length[a], S.length
+    planes = bs.estimate(A, w, N)
+    for m, key in enumerate(["ip", "ham", "js", "cos"]):
+        f32 = bs.estimate_scores(A, w, N, key, torch.float32, popA=pop[a].contiguous())
+        f64 = bs.estimate_scores(A, w, N, key, torch.float64)
+        torch.cuda.synchronize()
+        assert torch.equal(f64, planes[key]), key
+        want = np.array([[oracle.score_f32(xa[i], xb[j], X[i, j], N, m) for j in range(len(xb))]
+                         for i in range(len(a))], np.float32)
+        got = f32.cpu().numpy()
+        bad = np.nonzero(got.view(np.uint32) != want.view(np.uint32))
+        assert len(bad[0]) == 0, (key, bad[0][:3], bad[1][:3], got[bad][:3], want[bad][:3])
