@@ -361,9 +361,17 @@ def ranking_eval(dev, max_queries=500, widths=(256, 1024, 4096)):
     return out
 
 
-def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256, steps=600, batch=65536):
+def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256, steps=(600, 1500, 3000, 6000),
+                 batch=65536):
     """Learned estimator vs closed form: train on ~10M near-duplicate pairs of
-    the benchmark distribution sketched at N = 256, test on ~1M held-out pairs."""
+    the benchmark distribution sketched at N = 256, test on ~1M held-out pairs.
+    One network per training length (cosine schedule over its own length), so
+    the held-out MSE against the step count shows where training converges;
+    the longest run is also scored per saturation bucket of x_u / N
+    (x_u = |a_s OR b_s|), next to the closed form and to the empirical mean
+    label of each exact count triple seen in training (a lookup-table
+    predictor, the reference for what the three counts allow)."""
+    import numpy as np
     import torch
 
     import datagen
@@ -377,17 +385,56 @@ def learned_eval(dev, n_train_groups=20000, n_test_groups=2000, group=32, N=256,
     dtr = learned.sketch_pairs(tr, pi, N, dev)
     dte = learned.sketch_pairs(te, pi, N, dev)
     del tr, te
-    model = learned.Model(learned.init_master(0, dev))
-    torch.cuda.synchronize()
-    t = time.time()
-    model.train(dtr, steps=steps, batch=batch, lr=3e-3, seed=0)
-    torch.cuda.synchronize()
-    t_train = time.time() - t
-    pred = model.predict(dte)
     base = learned.closed_form(dte)
-    out = {"N": N, "train_pairs": len(dtr), "heldout_pairs": len(dte), "steps": steps, "batch": batch,
-           "mse_learned": learned.mse(pred, dte), "mse_closed_form": learned.mse(base, dte),
-           "train_seconds": t_train, "data_seconds": t_gen}
+    curve = []
+    model = None
+    for st in steps:
+        model = learned.Model(learned.init_master(0, dev))
+        torch.cuda.synchronize()
+        t = time.time()
+        model.train(dtr, steps=st, batch=batch, lr=3e-3, seed=0)
+        torch.cuda.synchronize()
+        curve.append({"steps": st, "train_seconds": time.time() - t,
+                      "mse_learned": learned.mse(model.predict(dte), dte)})
+    pred = model.predict(dte)
+    out = {"N": N, "train_pairs": len(dtr), "heldout_pairs": len(dte), "batch": batch, "steps": steps[-1],
+           "mse_learned": curve[-1]["mse_learned"], "mse_closed_form": learned.mse(base, dte),
+           "train_seconds": curve[-1]["train_seconds"], "data_seconds": t_gen, "convergence": curve}
+
+    # per-bucket errors on the held-out pairs
+    xa, xb, xab = (v.cpu().numpy().astype(np.int64) for v in (dte.xa, dte.xb, dte.xab))
+    lab = dte.label.cpu().numpy().astype(np.float64)
+    pl = pred.cpu().numpy().astype(np.float64)
+    pc = base.cpu().numpy().astype(np.float64)
+    # lookup-table reference: mean training label per exact (x_a, x_b, x_ab)
+    txa, txb, txab = (v.cpu().numpy().astype(np.int64) for v in (dtr.xa, dtr.xb, dtr.xab))
+    M = N + 1
+    tkey = (txa * M + txb) * M + txab
+    keys, inv = np.unique(tkey, return_inverse=True)
+    tmean = np.bincount(inv, weights=dtr.label.cpu().numpy().astype(np.float64)) / np.bincount(inv)
+    hkey = (xa * M + xb) * M + xab
+    pos = np.clip(np.searchsorted(keys, hkey), 0, len(keys) - 1)
+    seen = keys[pos] == hkey
+    plut = np.where(seen, tmean[pos], np.nan)
+    xu = (xa + xb - xab) / N
+    edges = [0.0, 0.5, 0.75, 0.9, 0.97, 1.0001]
+    buckets = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        m = (xu >= lo) & (xu < hi)
+        ms = m & seen
+        if not m.any():
+            continue
+        buckets.append({"xu_over_N": [lo, min(hi, 1.0)], "pairs": int(m.sum()),
+                        "mse_learned": float(np.mean((pl[m] - lab[m]) ** 2)),
+                        "mse_closed_form": float(np.mean((pc[m] - lab[m]) ** 2)),
+                        "lookup_coverage": float(ms.sum() / m.sum()),
+                        "mse_lookup_on_covered": float(np.mean((plut[ms] - lab[ms]) ** 2)) if ms.any() else None,
+                        "mse_learned_on_covered": float(np.mean((pl[ms] - lab[ms]) ** 2)) if ms.any() else None})
+    out["by_saturation"] = buckets
+    out["lookup_reference"] = {"coverage": float(seen.mean()),
+                               "mse_lookup_on_covered": float(np.mean((plut[seen] - lab[seen]) ** 2)),
+                               "mse_learned_on_covered": float(np.mean((pl[seen] - lab[seen]) ** 2)),
+                               "mse_closed_form_on_covered": float(np.mean((pc[seen] - lab[seen]) ** 2))}
     # inference throughput on the held-out pairs
     ws = bs.mlp_workspace(len(dte), N, dev)
     o = torch.empty(len(dte), dtype=torch.float32, device=dev)
@@ -507,10 +554,9 @@ def batch_eval(dev, n_problems=64, k=100, reps=5, check=4):
     return out
 
 
-def cpu_baseline(corpus, queries, pi, N, k, nq):
-    """The CPU oracle (plain C, OpenMP over rows) on a bounded sample."""
-    import numpy as np
-
+def cpu_baseline(corpus, queries, pi, N, k, nq, nq_single=16):
+    """The CPU oracle (plain C, OpenMP over rows) on a bounded sample, on all
+    the host cores it may use and on one thread."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     used = oracle.set_threads(threads)
@@ -524,11 +570,27 @@ def cpu_baseline(corpus, queries, pi, N, k, nq):
     oracle.topk(sub, S, N, oracle.JS, k)
     t_tk = time.perf_counter() - t
     pairs = nq * corpus.n
+    # one thread, on fewer queries
+    oracle.set_threads(1)
+    sub1 = oracle.Sets(SQ.vals, SQ.start[:nq_single], SQ.length[:nq_single])
+    t = time.perf_counter()
+    oracle.topk(sub1, S, N, oracle.JS, k)
+    t_1 = time.perf_counter() - t
+    t = time.perf_counter()
+    S1 = oracle.sketch_sets(corpus.indptr, corpus.indices, corpus.d, pi, N)
+    oracle.pack(S1, N)
+    t_sk1 = time.perf_counter() - t
+    oracle.set_threads(threads)
     return {"value": pairs / t_tk, "unit": "pair estimates/s", "cores": used, "kind": "oracle",
             "sample": "oracle top-%d Jaccard of %d queries x %d corpus rows at N=%d (%.1f s); "
                       "oracle sketch of all %d corpus rows (%.2f s)" % (
                           k, nq, corpus.n, N, t_tk, corpus.n, t_sk),
-            "sketch_vectors_per_s": corpus.n / t_sk}
+            "sketch_vectors_per_s": corpus.n / t_sk,
+            "single_thread": {"value": nq_single * corpus.n / t_1, "unit": "pair estimates/s", "cores": 1,
+                              "sample": "oracle top-%d Jaccard of %d queries x %d corpus rows at N=%d (%.1f s); "
+                                        "oracle sketch of all %d corpus rows (%.2f s)" % (
+                                            k, nq_single, corpus.n, N, t_1, corpus.n, t_sk1),
+                              "sketch_vectors_per_s": corpus.n / t_sk1}}
 
 
 def main():
@@ -600,7 +662,7 @@ def main():
         if "topk_scan" not in kt:
             return None
         t = kt["topk_scan"]["avg_ms"] / 1e3
-        if N % 512 == 0:
+        if N % 256 == 0:
             # matrix-core scan: x_ab of every scanned pair is an N-term 0/1
             # product, 2 N flops on FP4 operands
             fl = 2 * nQ * (nC - S) * N
@@ -652,7 +714,7 @@ def main():
                    "row_length": "round(lognormal), mean 230, sd 150",
                    "feature_popularity": "Zipf(1.1)", "score_dtype": "f32",
                    "pair_counts": "exact integers: 0/1 FP4 matrix-core operands with FP32 accumulators "
-                                  "(N a multiple of 512), else VALU AND + popcount", "parallelism": "single GPU"},
+                                  "(N a multiple of 256), else VALU AND + popcount", "parallelism": "single GPU"},
         "sketched_vectors_per_s": sketch_rate(kt),
         "pair_estimates_per_s": value,
         "kernels_ms": {n: v["avg_ms"] for n, v in kt.items()},

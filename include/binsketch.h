@@ -270,7 +270,7 @@ bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ, const uint
  *     1 <= k <= min(n_rows, BS_MAX_K); nnz and q_nnz < 2^31.
  *   bs_batch_shape  the scan tile shape used for one width: 64-query groups
  *     per wave (qpl; 1 for widths that scan on the matrix cores, N a
- *     multiple of 512) and the scan grid size in waves (0 = built-in rule);
+ *     multiple of 256) and the scan grid size in waves (0 = built-in rule);
  *     ms is the time the autotuner measured for that width's top-k stages
  *     (-1 if not tuned).
  *
@@ -421,7 +421,7 @@ int bs_debug_set_topk_tau_rank(int64_t rank);
 /*
  * Testing hook, not for production callers: with on = 0, bs_topk forms the
  * pair counts of its scan on the vector ALU (AND + popcount per word) even
- * where the matrix-core scan applies (N a multiple of 512, more than 64
+ * where the matrix-core scan applies (N a multiple of 256, more than 64
  * queries); any other value restores the automatic choice. The two scans
  * produce the same candidates; lets tests cover both. bs_topk_workspace_size
  * follows the same choice, so size the workspace after setting it.

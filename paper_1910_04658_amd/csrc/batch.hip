@@ -45,7 +45,7 @@ std::vector<TopkTune> candidate_tunes(int32_t N) {
   const int qpls[3] = {1, 2, 4};
   // the word-split scan (256 and 512 words) also tries a finer grid
   const int waves[4] = {4096, 8192, 16384, 32768};
-  if (N % 512 == 0) {  // the matrix-core scan: only the grid size varies
+  if (N % 256 == 0) {  // the matrix-core scan: only the grid size varies
     for (int w : waves) {
       TopkTune t;
       t.qpl = 1;

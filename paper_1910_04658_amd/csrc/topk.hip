@@ -16,15 +16,15 @@
 //     probability below 1e-9 (a Poisson tail; kt = k when the sample is the
 //     corpus), so tau is almost always <= the true k-th best score and the
 //     candidates are about kt * nC / S rather than k * nC / S.
-//  2. scan: every other (query, corpus row) pair. For N a multiple of 512 the
+//  2. scan: every other (query, corpus row) pair. For N a multiple of 256 the
 //     pair counts of a query batch against the corpus are formed on the
 //     matrix cores as a product of 0/1 matrices (FP4 operands, exact FP32
 //     counts); otherwise lanes hold queries (words in VGPRs) and corpus rows
 //     arrive on the scalar unit. Instead of evaluating the score (an IEEE
 //     division per pair) both test x_ab >= m[x_c][q], a per-query integer
 //     bound that every pair scoring >= tau satisfies, and write the survivors
-//     (a few percent) into the query's own slot range for that corpus slab,
-//     numbered without atomics.
+//     (about 1%) into the query's own slot range for that corpus slab, with
+//     no global atomics.
 //  3. select: per query, the sample and slab candidates are compacted (block
 //     scan over slab counts), scored exactly as unique 64-bit keys (score
 //     key, then inverted index), the k-th key found by radix select and the
@@ -65,9 +65,14 @@ constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the 
 constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, about
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFallbackBlocks = 16;
-constexpr int kMmaT = 4;             // 16-row MFMA tiles per wave tile of the matrix-core scan
-constexpr int kMmaRows = 16 * kMmaT; // corpus rows per wave tile
-constexpr int kMmaWaves = 16384;     // waves of the matrix-core scan grid, about
+constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
+#ifndef BS_EXP_MMA_WAVES
+#define BS_EXP_MMA_WAVES 16384
+#endif
+constexpr int kMmaWaves = BS_EXP_MMA_WAVES;     // waves of the matrix-core scan grid, about
+constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
+constexpr int kMmaQCap = 256;         // survivor queue entries per wave of the matrix-core scan
+constexpr int kMmaHoldChunks = 2;     // the matrix-core scan holds a group's query words in registers up to this many chunks
 
 struct QConst {  // per-query constants written by the sample pass
   float tau;     // (a lower bound on) the kt-th best sample score
@@ -140,9 +145,9 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   // Sketches of 256 or 512 words do not fit one lane's registers: four waves
   // share a 64-query group, each holding a quarter of the words.
   p.split = !p.rows && pow2 && (W32 == 256 || W32 == 512);
-  // Widths of whole 512-bit chunks scan on the matrix cores (the word-split
+  // Widths of whole 256-bit chunks scan on the matrix cores (the word-split
   // sample pass is kept for the wide ones).
-  p.mma = !p.rows && tune.mma != 0 && N % 512 == 0;
+  p.mma = !p.rows && tune.mma != 0 && N % 256 == 0;
   if (p.rows || p.split || p.mma) p.qpl = 1;
   if (p.mma) {
     p.ngrp = nqb;
@@ -240,7 +245,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.off_qovf = take(nQs * 4);
 
   p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
-  p.off_mtab = take((size_t)(N + 1) * (size_t)((nQ + 63) / 64 * 64) * 2);
+  p.off_mtab = take((size_t)(N + 2) * (size_t)((nQ + 63) / 64 * 64) * 2);  // rows 0..N, then N + 1: all 65535
   p.off_ovf = take((nQs + 2) * 4);
   p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
@@ -467,7 +472,7 @@ struct TopkArgs {
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
   uint64_t* __restrict__ scratch;  // [F][nC]
-  uint16_t* __restrict__ mtab;     // [N+1][nQp] pair-count thresholds
+  uint16_t* __restrict__ mtab;     // [N+2][nQp] pair-count thresholds (row N+1: 65535)
   int32_t* __restrict__ ovf;       // [2 + nQ]: count, key buffers taken, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
@@ -857,9 +862,9 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     const int xc = (int)by * kBoundX + wid + r * RW;
-    if (xc > a.N) break;
-    uint16_t m = 65535;
-    if (q_ok) {
+    if (xc > a.N + 1) break;
+    uint16_t m = 65535;  // row N + 1 and queries past the batch: no count of N < 65536 reaches it
+    if (q_ok && xc <= a.N) {
       const int X = base[r] + (tv[r] <= bnd[r] ? 1 : 0) - 1;
       const int64_t mm = (int64_t)k.xq + xc - X;
       m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
@@ -1177,31 +1182,34 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
   return ((uint64_t)score_key<M>(sc) << 32) | (uint64_t)(~idx);
 }
 
-// Matrix-core scan. The pair counts of 16 queries x 16 corpus rows are one
+// Matrix-core scan. The pair counts of 32 queries x 32 corpus rows are one
 // product of 0/1 matrices over the N sketch bits (x_ab = sum over bits of
 // q_bit * c_bit), formed exactly on the matrix cores with FP4 (E2M1)
-// operands. A 512-bit chunk of a row is held by a 16-lane column of the
-// wave as 16 words (lane l: row l % 16, words 4 (l / 16) .. +3), and bit
-// class d (bits 4i + d of every word) becomes an FP4 operand by a mask
+// operands. A 256-bit chunk of a row is held by two lanes of the wave, 16
+// bytes each (lane l: row l % 32, words 4 (l / 32) .. +3 of the chunk), and
+// bit class d (bits 4i + d of every word) becomes an FP4 operand by a mask
 // alone: class 0 keeps nibble bit 0 (the value 0.5), class 1 bit 1 (1.0),
 // class 2 bit 2 (2.0), and class 3 is shifted down three places (0.5). Each
-// class is one v_mfma_scale_f32_16x16x128_f8f6f4 whose block scales make
+// class is one v_mfma_scale_f32_32x32x64_f8f6f4 whose block scales make
 // every product of two set bits exactly 1.0, so the FP32 accumulators hold
 // exact counts (N <= 2^24). A and B take the same bit order, so the product
-// is the plain AND-popcount whatever order the unit sums in.
+// is the plain AND-popcount whatever order the unit sums in. The 32 x 32
+// shape does twice the work of a 16 x 16 x 128 product per instruction and
+// needs a quarter of the accumulator chains for the same tile, which keeps
+// the matrix cores far busier at two waves per SIMD.
 //
-// A wave owns one 64-query group and the rows of its slab in tiles of
-// 16 kMmaT rows (4 x kMmaT MFMA tiles, 16 kMmaT accumulators per lane); the four waves of a block
-// take four query groups of the same slab. The epilogue reads, per lane and
-// row, the bounds m[x_c][q] of its 16 queries, one 32-byte run of the table
-// row (for four or more chunks copied to LDS while the tile is multiplied);
-// survivors are numbered by wave ballots, no atomics.
+// A wave owns one 64-query group and the rows of its slab in tiles of 64
+// rows (2 x 2 products of 32 x 32, 64 accumulators per lane); the four
+// waves of a block take four query groups of the same slab. The epilogue
+// reads, per lane and row, the bounds m[x_c][q] of its 16 queries, one
+// 32-byte run of the table row (for eight or more chunks copied to LDS
+// while the tile is multiplied). Survivors are numbered through an LDS
+// queue (below), no global atomics.
 typedef int bs_v8i __attribute__((ext_vector_type(8)));
-typedef float bs_v4f __attribute__((ext_vector_type(4)));
+typedef float bs_v16f __attribute__((ext_vector_type(16)));
 
 template <int D>
-__device__ __forceinline__ bs_v8i fp4_class(uint2 lo, uint2 hi) {
-  const uint32_t w[4] = {lo.x, lo.y, hi.x, hi.y};
+__device__ __forceinline__ bs_v8i fp4_class(const uint32_t (&w)[4]) {
   bs_v8i r = {0, 0, 0, 0, 0, 0, 0, 0};  // FP4 operands use the low four words
 #pragma unroll
   for (int j = 0; j < 4; ++j)
@@ -1212,84 +1220,109 @@ __device__ __forceinline__ bs_v8i fp4_class(uint2 lo, uint2 hi) {
 
 // E8M0 block scale of class D: 2 for the 0.5 classes, 1, 1/2 for the 2.0 class
 template <int D>
-__device__ __forceinline__ bs_v4f mma_class(bs_v8i a, bs_v8i b, bs_v4f c) {
+__device__ __forceinline__ bs_v16f mma_class(bs_v8i a, bs_v8i b, bs_v16f c) {
   constexpr int sc = D == 1 ? 127 : (D == 2 ? 126 : 128);
-  return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 4, 4, 0, sc, 0, sc);
+  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, sc, 0, sc);
 }
 
-// KCT: 512-bit chunks per row when fixed at compile time (the chunk loop is
+// Blocks are handed to the eight XCDs in turn (block b to XCD b % 8), and each
+// XCD has its own L2. This renumbering gives every XCD one contiguous run of
+// the `total` blocks (a bijection of [0, total)), so blocks with neighbouring
+// numbers share an L2 and run at about the same time. In a persistent grouped
+// launch the grid is a multiple of 8, so item-local numbers of one residue
+// class still share an XCD.
+__device__ __forceinline__ int64_t xcd_contiguous(int64_t b, int64_t total) {
+  const int64_t q = total / kXcds, r = total % kXcds;
+  const int64_t x = b % kXcds, j = b / kXcds;
+  return x * q + (x < r ? x : r) + j;
+}
+
+// KCT: 256-bit chunks per row when fixed at compile time (the chunk loop is
 // then unrolled, which keeps the accumulators in place), 0 for any width.
 template <int KCT>
-__device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
+__device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int i = lane % 16, g = lane / 16;
+  const int c = lane % 32, h = lane / 32;
+  // the nqb4 blocks of a slab read the same corpus rows: one L2 for all of them
+  const int64_t bid = xcd_contiguous(vbid, a.n_slabs * a.nqb4);
   const int64_t sl = bid / a.nqb4, qgb = bid % a.nqb4;
   const int64_t qg = qgb * (kThreads / kWave) + wid;  // 64-query group
   const int64_t c_begin = sl * a.slab;
   const int64_t c_end = c_begin + a.slab < a.nC ? c_begin + a.slab : a.nC;
   if (qg * kWave >= a.nQ || c_begin >= c_end) return;  // wave-uniform
-  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 16;
+  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 8;
   const int32_t ntiles = (int32_t)((c_end - c_begin + kMmaRows - 1) / kMmaRows);
   // Operands are read as a uniform base (scalar registers) plus a 32-bit lane
-  // offset. A rows: query qg*64 + 16 qb + i (past the batch: the last query,
-  // whose lanes are masked out of every survivor ballot); B rows: tile row
-  // 16 t + i (past the slab: its last row, masked in the epilogue).
+  // offset. A rows: a query of the group (past the batch: the last query);
+  // B rows: tile row 32 ct + c (past the slab: its last row).
   const uint32_t rowb = (uint32_t)W32 * 4u;  // bytes per row
   const char* qbase = reinterpret_cast<const char*>(a.Q) + (size_t)qg * kWave * rowb;
   const char* cslab = reinterpret_cast<const char*>(a.C) + (size_t)c_begin * rowb;
   const uint32_t nrows = (uint32_t)(c_end - c_begin);
-  // Query order: row i of 16-query tile qb is query 16 (i / 4) + 4 qb + i % 4
-  // of the group, so the 16 queries whose counts a lane of group g holds
-  // (result rows 4 g .. 4 g + 3 of every tile) are the consecutive queries
-  // 16 g .. 16 g + 15, and their bounds are one 32-byte run of a table row.
-  uint32_t qoff[4];
+  // Query order: operand row m of 32-query tile qt is query
+  // 32 qt + 16 ((m / 4) % 2) + 4 (m / 8) + m % 4 of the group. The product's
+  // rows 8 j + 4 h + r (j, r = 0..3) that lane (h, c) holds are then the
+  // consecutive queries 32 qt + 16 h + 4 j + r, so accumulator element e of a
+  // lane is query 32 qt + 16 h + e, and its 16 bounds per row are one 32-byte
+  // run of a table row.
+  uint32_t qoff[2];
 #pragma unroll
-  for (int qb = 0; qb < 4; ++qb) {
-    int64_t q = qg * kWave + 16 * (i / 4) + 4 * qb + i % 4;
+  for (int qt = 0; qt < 2; ++qt) {
+    int64_t q = qg * kWave + 32 * qt + 16 * ((c / 4) % 2) + 4 * (c / 8) + c % 4;
     q = q < a.nQ ? q : a.nQ - 1;
-    qoff[qb] = (uint32_t)(q - qg * kWave) * rowb + 16u * g;
+    qoff[qt] = (uint32_t)(q - qg * kWave) * rowb + 16u * h;
   }
-  auto load_a = [&](int ch, uint2 (&qa)[4][2]) {
+  auto load_a = [&](int ch, uint32_t (&qa)[2][4]) {
 #pragma unroll
-    for (int qb = 0; qb < 4; ++qb) {
-      const uint2* p = reinterpret_cast<const uint2*>(qbase + (qoff[qb] + 64u * ch));
-      qa[qb][0] = p[0];
-      qa[qb][1] = p[1];
+    for (int qt = 0; qt < 2; ++qt) {
+      const uint4 v = *reinterpret_cast<const uint4*>(qbase + (qoff[qt] + 32u * ch));
+      qa[qt][0] = v.x;
+      qa[qt][1] = v.y;
+      qa[qt][2] = v.z;
+      qa[qt][3] = v.w;
     }
   };
-  auto load_b = [&](int32_t tile, int ch, uint2 (&cb)[kMmaT][2]) {
+  auto load_b = [&](int32_t tile, int ch, uint32_t (&cb)[2][4]) {
 #pragma unroll
-    for (int t = 0; t < kMmaT; ++t) {
-      uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
+    for (int ct = 0; ct < 2; ++ct) {
+      uint32_t r = (uint32_t)tile * kMmaRows + 32u * ct + c;
       r = r < nrows ? r : nrows - 1;
-      const uint2* p = reinterpret_cast<const uint2*>(cslab + (r * rowb + 16u * g + 64u * ch));
-      cb[t][0] = p[0];
-      cb[t][1] = p[1];
+      const uint4 v = *reinterpret_cast<const uint4*>(cslab + (r * rowb + 16u * h + 32u * ch));
+      cb[ct][0] = v.x;
+      cb[ct][1] = v.y;
+      cb[ct][2] = v.z;
+      cb[ct][3] = v.w;
     }
   };
-  auto load_xc = [&](int32_t tile, int32_t (&xc)[kMmaT]) {
+  auto load_xc = [&](int32_t tile, int32_t (&xc)[2]) {
 #pragma unroll
-    for (int t = 0; t < kMmaT; ++t) {
-      uint32_t r = (uint32_t)tile * kMmaRows + 16u * t + i;
+    for (int ct = 0; ct < 2; ++ct) {
+      uint32_t r = (uint32_t)tile * kMmaRows + 32u * ct + c;
       r = r < nrows ? r : nrows - 1;
-      xc[t] = a.popC[c_begin + r];
+      xc[ct] = a.popC[c_begin + r];
     }
   };
-  // The bounds of a tile, m[x_c(r)][qg*64 .. qg*64+63] for its 64 rows r (128
-  // bytes each), are copied into the wave's LDS region by eight 16-byte-per-
-  // lane LDS-direct loads issued when the tile starts, so they arrive while
-  // it is multiplied. Load j, lane l: row R = 8 j + l / 8 lands at slot
-  // s = l % 8 and carries piece s ^ (R & 7) of the row (spreads the
-  // epilogue's reads over the banks); x_c(R) comes from lane R % 16, which
-  // holds it in xc[R / 16].
+  // Bounds m[x][q] of the tile's rows. A row that must yield no survivor
+  // (past the slab, or a sampled row, already scored by the sample pass)
+  // takes table row N + 1, which holds 65535 for every query; so do the
+  // table's columns of queries past the batch. For N < 65536 a count never
+  // reaches 65535, so the compare alone decides; at N = 65536 the epilogue
+  // also masks rows and queries explicitly.
+  // For four or more chunks the bounds of a tile (64 rows x 128 bytes) are
+  // copied into the wave's LDS region by eight 16-byte-per-lane LDS-direct
+  // loads issued when the tile starts, so they arrive while it is
+  // multiplied. Load j, lane l: row R = 8 j + l / 8 lands at slot s = l % 8
+  // and carries piece s ^ (R & 7) of the row (spreads the epilogue's reads
+  // over the banks); its table row comes from lane R % 32, which holds it in
+  // xb[R / 32]. Shorter tiles read the bounds from the table in the epilogue.
   __shared__ uint4 mlds[kThreads / kWave][kMmaRows * 8];
   uint4* const mw = mlds[wid];
   const uint16_t* const mq = a.mtab + qg * kWave;
-  auto bounds_to_lds = [&](const int32_t (&xt)[kMmaT]) {
+  auto bounds_to_lds = [&](const int32_t (&xt)[2]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const uint32_t R = 8u * j + lane / 8, piece = (lane % 8) ^ (R & 7);
-      const int32_t x = __shfl(xt[j / 2], (int)(R % 16));
+      const int32_t x = __shfl(xt[j / 4], (int)(R % 32));
       const uint16_t* src = mq + (size_t)(uint32_t)x * (size_t)a.nQp + 8 * piece;
       __builtin_amdgcn_global_load_lds(src, mw + 64 * j, 16, 0, 0);
     }
@@ -1299,113 +1332,80 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
   const uint32_t s_end = (uint32_t)s_end64;
   // first sampled row at or after the slab start (rows past s_end are never sampled)
   uint32_t next_s = (uint32_t)((c_begin + a.stride - 1) / a.stride * a.stride);
-  // Survivors of query (qb, g, rr) = qg*64 + 16 g + 4 qb + rr are numbered by
-  // a ballot over the 16 lanes of group g; cnt[qb][rr] holds the group's
-  // running count (the same in its 16 lanes). Slot s of that query lies at
-  // cbase + (4 qb + rr) * kmax + s * n_slabs.
-  uint64_t* const cbase = a.cands + (size_t)(qg * kWave + 16 * g) * a.kmax + a.S + sl;
-  const int32_t scap = (int32_t)a.scap;
+  // Survivors are first appended to the wave's LDS queue as finished
+  // entries, each with its query (a byte beside it), at positions from a
+  // ballot prefix count (one queue head for the wave). The queue is drained
+  // when nearly full and once at the end of the slab: an LDS atomic on the
+  // query's counter gives each entry its slot s, stored at
+  // cands[q * kmax + S + s * n_slabs + sl]. Slot order within a query does
+  // not matter (the select orders candidates by their keys). Draining rarely
+  // keeps global stores, and the waits on them, out of the tile loop.
+  __shared__ uint64_t sq_lds[kThreads / kWave][kMmaQCap];
+  __shared__ uint8_t sqq_lds[kThreads / kWave][kMmaQCap];
+  __shared__ uint32_t sc_lds[kThreads / kWave][kWave];
+  uint64_t* const squeue = sq_lds[wid];
+  uint8_t* const squery = sqq_lds[wid];
+  uint32_t* const scount = sc_lds[wid];
+  scount[lane] = 0u;
+  uint64_t* const cbase = a.cands + (size_t)(qg * kWave) * a.kmax + a.S + sl;
+  const uint32_t scap = (uint32_t)a.scap;
   const uint32_t nsl = (uint32_t)a.n_slabs;
-  const uint64_t gmask = 0xffffull << (16 * g);
-  // Lanes whose query (qb, g, rr) lies inside the batch: query 16 g + 4 qb + rr
-  // of the group exists iff g < ceil((nrem - 4 qb - rr) / 16). Queries past the
-  // batch hold the last real query's words and must never store a survivor,
-  // whatever their bound (a count can reach the 16-bit bound at N = 65536).
-  const int32_t nrem = (int32_t)(a.nQ - qg * kWave < kWave ? a.nQ - qg * kWave : kWave);
-  auto qvalid = [&](int qb, int rr) -> uint64_t {
-    const int32_t c = nrem - 4 * qb - rr;
-    const int32_t ng = c <= 0 ? 0 : ((c + 15) / 16 < 4 ? (c + 15) / 16 : 4);
-    return ng >= 4 ? ~0ull : ((1ull << (16 * ng)) - 1ull);
+  uint32_t qn = 0;  // queued entries (wave-uniform)
+  auto drain = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t b = 0; b < qn; b += kWave) {
+      if (b + (uint32_t)lane < qn) {
+        const uint64_t e = squeue[b + lane];
+        const uint32_t qid = squery[b + lane];
+        const uint32_t slot = atomicAdd(&scount[qid], 1u);
+        if (slot < scap) cbase[(size_t)qid * a.kmax + (size_t)slot * nsl] = e;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    qn = 0;
   };
-  int32_t cnt[4][4];
-#pragma unroll
-  for (int qb = 0; qb < 4; ++qb)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) cnt[qb][rr] = 0;
+  // At N = 65536 a count can reach the 65535 of the masked bounds: lanes of
+  // queries past the batch and of rows to skip are masked out of every
+  // ballot there.
+  const bool explicit_mask = a.N >= 65536;
+  const int32_t nrem = (int32_t)(a.nQ - qg * kWave < kWave ? a.nQ - qg * kWave : kWave);
+  auto qvalid = [&](int qt, int e) -> uint64_t {
+    const uint64_t lo = 32 * qt + e < nrem ? 0xffffffffull : 0ull;
+    const uint64_t hi = 32 * qt + 16 + e < nrem ? 0xffffffff00000000ull : 0ull;
+    return lo | hi;
+  };
+  const int32_t xskip = a.N + 1;  // the table row of 65535s
 
   // software pipeline: the operands of the next (tile, chunk) step load while
   // the current one is multiplied; the row weights of the next tile load
   // during the current tile's epilogue
   // with at most two chunks the query words stay in registers for the whole slab
-  constexpr bool HOLD = KCT > 0 && KCT <= 2;
-  uint2 qh[HOLD ? KCT : 1][4][2];
+  constexpr bool HOLD = KCT > 0 && KCT <= kMmaHoldChunks;
+  uint32_t qh[HOLD ? KCT : 1][2][4];
   if constexpr (HOLD) {
 #pragma unroll
     for (int ch = 0; ch < KCT; ++ch) load_a(ch, qh[ch]);
   }
-  uint2 qa[4][2], cb[kMmaT][2];
+  uint32_t qa[2][4], cb[2][4];
   if constexpr (!HOLD) load_a(0, qa);
   load_b(0, 0, cb);
-  int32_t xc[kMmaT];
+  int32_t xc[2];
   load_xc(0, xc);
   // With four or more chunks a tile is long enough to hide the copy of its
-  // bounds; shorter ones read them from the table in the epilogue.
+  // bounds. The epilogue waits for the copy with vmcnt(VM_AFTER): the vector
+  // memory operations issued after it are the operand loads of the tile's
+  // chunk steps (two per step, four without held query words), and they
+  // complete in order. Width-generic code (KCT = 0) waits for everything.
   constexpr bool LDSB = KCT == 0 || KCT >= 4;
+  constexpr int VM_AFTER0 = KCT * (HOLD ? 2 : 4);
+  constexpr int VM_AFTER = VM_AFTER0 > 63 ? 63 : VM_AFTER0;
+  constexpr int VM_WAIT = (VM_AFTER & 0xF) | ((VM_AFTER >> 4) << 14) | (0x7 << 4) | (0xF << 8);
   for (int32_t tile = 0; tile < ntiles; ++tile) {
-    if constexpr (LDSB) {
-      // the previous epilogue's reads of the region are done (their values
-      // were used); then this tile's bounds start their way into it
-      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-      bounds_to_lds(xc);
-    }
-    if constexpr (HOLD) {  // expand the held words anew per tile (hoisted, they would take 64 registers per chunk)
-#pragma unroll
-      for (int ch = 0; ch < (HOLD ? KCT : 1); ++ch)
-#pragma unroll
-        for (int qb = 0; qb < 4; ++qb) asm volatile("" : "+v"(qh[ch][qb][0]), "+v"(qh[ch][qb][1]));
-    }
-    bs_v4f acc[kMmaT][4];
-#pragma unroll
-    for (int t = 0; t < kMmaT; ++t)
-#pragma unroll
-      for (int qb = 0; qb < 4; ++qb) acc[t][qb] = bs_v4f{0.0f, 0.0f, 0.0f, 0.0f};
-    constexpr int KU = KCT > 0 && KCT <= 2 ? KCT : 1;
-#pragma unroll KU
-    for (int ch = 0; ch < KC; ++ch) {
-      // next step (the last step reloads itself: in bounds, unused)
-      const bool last = ch + 1 == KC;
-      const int32_t nt = last ? (tile + 1 < ntiles ? tile + 1 : tile) : tile;
-      const int nch = last ? (tile + 1 < ntiles ? 0 : ch) : ch + 1;
-      uint2 qn[4][2], cn[kMmaT][2];
-      if constexpr (!HOLD) load_a(nch, qn);
-      load_b(nt, nch, cn);
-      auto klass = [&](auto dc) {
-        constexpr int D = decltype(dc)::value;
-        bs_v8i A[4];
-#pragma unroll
-        for (int qb = 0; qb < 4; ++qb)
-          A[qb] = HOLD ? fp4_class<D>(qh[HOLD ? ch : 0][qb][0], qh[HOLD ? ch : 0][qb][1]) : fp4_class<D>(qa[qb][0], qa[qb][1]);
-#pragma unroll
-        for (int t = 0; t < kMmaT; ++t) {
-          const bs_v8i B = fp4_class<D>(cb[t][0], cb[t][1]);
-#pragma unroll
-          for (int qb = 0; qb < 4; ++qb) acc[t][qb] = mma_class<D>(A[qb], B, acc[t][qb]);
-        }
-      };
-      klass(std::integral_constant<int, 0>());
-      klass(std::integral_constant<int, 1>());
-      klass(std::integral_constant<int, 2>());
-      klass(std::integral_constant<int, 3>());
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if constexpr (!HOLD) {
-          qa[u][0] = qn[u][0];
-          qa[u][1] = qn[u][1];
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < kMmaT; ++u) {
-        cb[u][0] = cn[u][0];
-        cb[u][1] = cn[u][1];
-      }
-    }
-    // the next tile's row weights load during this tile's epilogue
-    int32_t xcur[kMmaT];
-#pragma unroll
-    for (int t = 0; t < kMmaT; ++t) xcur[t] = xc[t];
-    load_xc(tile + 1 < ntiles ? tile + 1 : tile, xc);
-    if constexpr (LDSB) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this tile's bounds are in LDS
-    // sampled rows of this tile (scored in the sample pass): one bit per row
+    // rows of this tile that yield no survivor: past the slab, or sampled
     const uint32_t r0 = (uint32_t)(c_begin + (int64_t)tile * kMmaRows);
     const uint32_t r_hi = (uint32_t)(c_begin + (int64_t)tile * kMmaRows + kMmaRows < c_end
                                          ? c_begin + (int64_t)tile * kMmaRows + kMmaRows
@@ -1415,58 +1415,138 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t bid) {
       smask |= 1ull << (next_s - r0);
       next_s += stride;
     }
+    int32_t xb[2];  // the bound table row of each of the lane's two rows
+    bool row_ok[2];
 #pragma unroll
-    for (int t = 0; t < kMmaT; ++t) {
-      const uint32_t r = r0 + 16 * t + i;
-      const bool row_ok = r < r_hi && !((smask >> (16 * t + i)) & 1);
-      const uint64_t rowm = __builtin_amdgcn_ballot_w64(row_ok);
-      const uint32_t R = 16u * t + i;
-      // bounds of queries 16 g .. 16 g + 15 for this row: pieces 2 g and 2 g + 1
-      uint4 mg[2];
-      if constexpr (LDSB) {
-        mg[0] = mw[R * 8 + ((2u * g) ^ (R & 7))];
-        mg[1] = mw[R * 8 + ((2u * g + 1) ^ (R & 7))];
-      } else {
-        const uint4* mrow =
-            reinterpret_cast<const uint4*>(mq + 16 * g + (size_t)(uint32_t)xcur[t] * (size_t)a.nQp);
-        mg[0] = mrow[0];
-        mg[1] = mrow[1];
-      }
+    for (int ct = 0; ct < 2; ++ct) {
+      const uint32_t R = 32u * ct + c;
+      row_ok[ct] = r0 + R < r_hi && !((smask >> R) & 1);
+      xb[ct] = row_ok[ct] ? xc[ct] : xskip;
+    }
+    if constexpr (LDSB) {
+      // the previous epilogue's reads of the region are done (their values
+      // were used); then this tile's bounds start their way into it
+      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+      bounds_to_lds(xb);
+    }
+    if constexpr (HOLD) {  // class operands formed anew per tile (hoisted, they would take 32 registers per chunk)
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) {
-        __builtin_amdgcn_sched_barrier(0);  // one 16-query tile at a time: short live ranges
-        const uint2 m2 = (qb & 1) ? make_uint2(mg[qb / 2].z, mg[qb / 2].w) : make_uint2(mg[qb / 2].x, mg[qb / 2].y);
-        const float m4[4] = {(float)(m2.x & 0xffffu), (float)(m2.x >> 16), (float)(m2.y & 0xffffu), (float)(m2.y >> 16)};
+      for (int ch = 0; ch < (HOLD ? KCT : 1); ++ch)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-          // counts and bounds are exact integers in FP32
-          const uint64_t bal = __builtin_amdgcn_ballot_w64(acc[t][qb][rr] >= m4[rr]) & rowm & qvalid(qb, rr);
-          if (bal) {  // wave-uniform
-            const bool take = (bal >> lane) & 1;
-            const uint64_t gb = bal & gmask;
-            const int32_t rank = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(gb >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)gb, 0u));
-            const int32_t slot = cnt[qb][rr] + rank;
-            if (take && slot < scap)
-              cbase[(size_t)(4 * qb + rr) * a.kmax + (uint32_t)slot * nsl] =
-                  raw_entry((uint32_t)acc[t][qb][rr], xcur[t], r, a.N);
-            cnt[qb][rr] += __popcll(gb);
+        for (int qt = 0; qt < 2; ++qt)
+          asm volatile("" : "+v"(qh[ch][qt][0]), "+v"(qh[ch][qt][1]), "+v"(qh[ch][qt][2]), "+v"(qh[ch][qt][3]));
+    }
+    bs_v16f acc[2][2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int qt = 0; qt < 2; ++qt)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[ct][qt][e] = 0.0f;
+    constexpr int KU = HOLD ? KCT : 1;
+#pragma unroll KU
+    for (int ch = 0; ch < KC; ++ch) {
+      // next step (the last step reloads itself: in bounds, unused)
+      const bool last = ch + 1 == KC;
+      const int32_t nt = last ? (tile + 1 < ntiles ? tile + 1 : tile) : tile;
+      const int nch = last ? (tile + 1 < ntiles ? 0 : ch) : ch + 1;
+      uint32_t qn4[2][4], cn[2][4];
+      if constexpr (!HOLD) load_a(nch, qn4);
+      load_b(nt, nch, cn);
+      auto klass = [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        bs_v8i A[2];
+#pragma unroll
+        for (int qt = 0; qt < 2; ++qt) A[qt] = HOLD ? fp4_class<D>(qh[HOLD ? ch : 0][qt]) : fp4_class<D>(qa[qt]);
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const bs_v8i B = fp4_class<D>(cb[ct]);
+#pragma unroll
+          for (int qt = 0; qt < 2; ++qt) acc[ct][qt] = mma_class<D>(A[qt], B, acc[ct][qt]);
+        }
+      };
+      klass(std::integral_constant<int, 0>());
+      klass(std::integral_constant<int, 1>());
+      klass(std::integral_constant<int, 2>());
+      klass(std::integral_constant<int, 3>());
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          if constexpr (!HOLD) qa[u][w] = qn4[u][w];
+          cb[u][w] = cn[u][w];
+        }
+    }
+    if constexpr (LDSB) {
+      if constexpr (KCT > 0) __builtin_amdgcn_s_waitcnt(VM_WAIT);  // this tile's bounds are in LDS
+      else __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
+    }
+    // the next tile's row weights load during this tile's epilogue
+    int32_t xcur[2];
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) xcur[ct] = xc[ct];
+    load_xc(tile + 1 < ntiles ? tile + 1 : tile, xc);
+    // the epilogue, with explicit row and query masks (EM) only at N = 65536
+    auto epilogue = [&](auto em_tag) {
+      constexpr bool EM = decltype(em_tag)::value;
+  #pragma unroll
+      for (int ct = 0; ct < 2; ++ct) {
+        const uint32_t R = 32u * ct + c;
+        const uint32_t r = r0 + R;
+        const uint64_t rowm = EM ? __builtin_amdgcn_ballot_w64(row_ok[ct]) : ~0ull;
+        // entry of a survivor (raw_entry): high word x_c << 16 | x_ab (x_ab
+        // alone at N = 65536), low word the row; its query 16 h + 32 qt + e
+        uint32_t hi_t = a.N < 65536 ? (uint32_t)xcur[ct] << 16 : 0u;
+        uint32_t qbase_t = 16u * h;
+        // formed anew per tile: hoisted out of the tile loop, the per-query
+        // values would take 64 registers
+        asm volatile("" : "+v"(qbase_t), "+v"(hi_t));
+  #pragma unroll
+        for (int qt = 0; qt < 2; ++qt) {
+          // bounds of queries 32 qt + 16 h .. + 15 for this row: pieces 4 qt + 2 h and + 1
+          const uint32_t p0 = 4u * qt + 2u * h;
+          uint4 mg[2];
+          if constexpr (LDSB) {
+            mg[0] = mw[R * 8 + (p0 ^ (R & 7))];
+            mg[1] = mw[R * 8 + ((p0 + 1) ^ (R & 7))];
+          } else {
+            const uint4* mrow = reinterpret_cast<const uint4*>(mq + 8 * p0 + (size_t)(uint32_t)xb[ct] * (size_t)a.nQp);
+            mg[0] = mrow[0];
+            mg[1] = mrow[1];
+          }
+  #pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            if (e % 4 == 0) __builtin_amdgcn_sched_barrier(0);  // four queries at a time: short live ranges
+            const uint4 m4 = mg[e / 8];
+            const uint32_t mw32 = (e % 8) / 2 == 0 ? m4.x : (e % 8) / 2 == 1 ? m4.y : (e % 8) / 2 == 2 ? m4.z : m4.w;
+            const float m = (float)(e % 2 == 0 ? (mw32 & 0xffffu) : (mw32 >> 16));
+            // counts and bounds are exact integers in FP32
+            const bool pass = acc[ct][qt][e] >= m;
+            uint64_t bal = __builtin_amdgcn_ballot_w64(pass);
+            if (EM) bal &= rowm & qvalid(qt, e);
+            if (bal) {  // wave-uniform
+              if (qn > (uint32_t)(kMmaQCap - kWave)) drain();
+              const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, qn));
+              if (EM ? ((bal >> lane) & 1) != 0 : pass) {
+                squeue[pos] = ((uint64_t)(hi_t | (uint32_t)acc[ct][qt][e]) << 32) | r;
+                squery[pos] = (uint8_t)(qbase_t + 32 * qt + e);
+              }
+              qn += (uint32_t)__popcll(bal);
+            }
           }
         }
       }
-    }
+    };
+    if (explicit_mask) epilogue(std::true_type());
+    else epilogue(std::false_type());
   }
-  // lane l reports query qg*64 + l = (g, qb, rr) = (l / 16, (l % 16) / 4, l % 4),
-  // a query of its own group
-  int32_t n = 0;
-#pragma unroll
-  for (int qb = 0; qb < 4; ++qb)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-      if (qb == i / 4 && rr == i % 4) n = cnt[qb][rr];
+  drain();
+  // lane l reports query qg*64 + l
+  const uint32_t n = scount[lane];
   const int64_t q = qg * kWave + lane;
   if (q < a.nQ) {
-    a.scnt[(size_t)q * a.n_slabs + sl] = n < scap ? n : scap;
+    a.scnt[(size_t)q * a.n_slabs + sl] = (int32_t)(n < scap ? n : scap);
     if (n > scap) a.qovf[q] = 1;
   }
 }
@@ -1852,7 +1932,7 @@ __global__ __launch_bounds__(kThreads) void topk_scan_split_kernel(GroupArgs g) 
   BS_GROUP_LOOP((scan_split_body<WS>(a, lb)))
 }
 template <bool ONE, int KCT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void topk_scan_mma_kernel(GroupArgs g) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void topk_scan_mma_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_mma_body<KCT>(a, lb)))
 }
 template <bool ONE, int M, int W32T>
@@ -1882,7 +1962,7 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
   switch (st) {
     case kStSample: return a.s_rblocks * a.s_nqb;
     case kStSampleSelect: return a.nQ;
-    case kStBound: return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 1 + kBoundX - 1) / kBoundX) : 0;
+    case kStBound: return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 2 + kBoundX - 1) / kBoundX) : 0;
     case kStScan:
       if (!scan) return 0;
       if (a.rows) return (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave);
@@ -1946,11 +2026,12 @@ const void* stage_kernel(const TopkArgs& a, int st) {
         }
       }
       if (a.mma) {
-        switch (W32 / 16) {
+        switch (W32 / 8) {  // 256-bit chunks per row
           case 1: return (const void*)topk_scan_mma_kernel<ONE, 1>;
           case 2: return (const void*)topk_scan_mma_kernel<ONE, 2>;
           case 4: return (const void*)topk_scan_mma_kernel<ONE, 4>;
           case 8: return (const void*)topk_scan_mma_kernel<ONE, 8>;
+          case 16: return (const void*)topk_scan_mma_kernel<ONE, 16>;
           default: return (const void*)topk_scan_mma_kernel<ONE, 0>;
         }
       }
@@ -2067,11 +2148,13 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
 
 }  // namespace
 
-// Overrides for tests of the overflow paths (negative = automatic).
-static int64_t g_scap_override = -1;
-static int64_t g_ldskeys_override = -1;
-static int64_t g_taurank_override = -1;
-static int32_t g_mma_override = -1;
+// Overrides for tests of the overflow paths (negative = automatic). Each
+// host thread has its own: a test's setting never reaches calls that other
+// threads make (a server's, say).
+static thread_local int64_t g_scap_override = -1;
+static thread_local int64_t g_ldskeys_override = -1;
+static thread_local int64_t g_taurank_override = -1;
+static thread_local int32_t g_mma_override = -1;
 
 // ---- group plans ----------------------------------------------------------------
 struct TopkGroup {

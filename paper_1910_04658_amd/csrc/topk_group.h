@@ -18,7 +18,7 @@ struct TopkTune {
   int32_t qpl = 0;    // 64-query groups per wave of the query-lane scan (1, 2 or 4; 2 for N <= 1024, 4 for N <= 512)
   int32_t waves = 0;  // approximate waves of the scan grid (sets the corpus slab length)
   int32_t rows = -1;  // 0: never use the row-lane scan; otherwise it is used for batches of <= 64 queries
-  int32_t mma = -1;   // 0: never use the matrix-core scan; otherwise it is used for N a multiple of 512
+  int32_t mma = -1;   // 0: never use the matrix-core scan; otherwise it is used for N a multiple of 256
 };
 
 struct TopkItem {

@@ -69,9 +69,10 @@ def test_scan_path_query_lanes(m, N, nq, dev):
 
 
 @pytest.mark.parametrize("m", [oracle.JS, oracle.COS])
-@pytest.mark.parametrize("N,nq", [(512, 70), (1024, 130), (4096, 65), (8192, 20), (16384, 33)])
+@pytest.mark.parametrize("N,nq", [(256, 70), (512, 70), (768, 100), (1024, 130), (4096, 65), (8192, 20),
+                                  (16384, 33)])
 def test_vector_and_matrix_scans_agree(m, N, nq, dev):
-    """Widths of whole 512-bit chunks scan on the matrix cores (FP4 products
+    """Widths of whole 256-bit chunks scan on the matrix cores (FP4 products
     of the sketch bits); with that switched off they take the vector-ALU
     scans (query lanes, or word-split for N >= 8192). Both give the oracle's
     result on sampled queries and identical results on all of them."""
@@ -213,7 +214,7 @@ def test_empty_and_saturated_rows(N, nq, dev):
     sketch. The last query is full, so in a ragged batch the query slots past
     the batch (which hold the last query's words) meet full corpus rows with
     x_ab = N; they must store nothing. Every scan that applies runs: the
-    matrix cores (N a multiple of 512, more than 64 queries or N > 4096) and
+    matrix cores (N a multiple of 256, more than 64 queries or N > 4096) and
     the vector ALU with them switched off (query lanes, word split, any width;
     row lanes for 9 queries up to N = 4096). All queries and all four
     measures against the oracle's full sort."""
@@ -227,7 +228,7 @@ def test_empty_and_saturated_rows(N, nq, dev):
     SC = oracle.sketch_sets(c.indptr, c.indices, N, pi, N)
     SQ = oracle.sketch_sets(qs.indptr, qs.indices, N, pi, N)
     assert SQ.length[-1] == N and (SC.length == N).any() and (SC.length == 0).any()
-    modes = [True, False] if N % 512 == 0 and (nq > 64 or N > 4096) else [True]
+    modes = [True, False] if N % 256 == 0 and (nq > 64 or N > 4096) else [True]
     for m in MEASURES:
         oi, osc = oracle.topk(SQ, SC, N, m, 50)
         for mma in modes:
