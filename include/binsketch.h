@@ -141,6 +141,27 @@ bs_status bs_sketch_parts(const bs_sketch_part* parts, int32_t n_parts, const in
                           void* stream);
 
 /*
+ * bs_sketch_prepare_map / bs_sketch_parts_prepared — bs_sketch_parts for a
+ * map pi that stays fixed across calls (the map is chosen once per (d, N),
+ * Section 3, the paragraph after the Definition): bs_sketch_prepare_map
+ * bit-packs pi into `map` once (the form bs_sketch builds in its workspace on
+ * every call) and reports values outside [0, N) through err_flag
+ * (BS_FLAG_MAP); bs_sketch_parts_prepared then sketches with that packed map
+ * and no packing launch. Outputs are exactly those of bs_sketch_parts.
+ *   map        device buffer of bs_sketch_workspace_size(d, N) bytes,
+ *              16-byte aligned; written by prepare, only read afterwards
+ *              (calls may overlap). pi must be the map it was prepared from
+ *              (it is still read when the packed map does not fit in LDS).
+ * Returns as bs_sketch_parts; BS_ERR_WORKSPACE for a NULL, short or
+ * misaligned map.
+ */
+bs_status bs_sketch_prepare_map(const int32_t* pi, int64_t d, int32_t N, int32_t* err_flag, void* map,
+                                size_t map_bytes, void* stream);
+bs_status bs_sketch_parts_prepared(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi, int64_t d,
+                                   int32_t N, const void* map, size_t map_bytes, int32_t* err_flag,
+                                   void* stream);
+
+/*
  * bs_and_popcount — all-pairs sketch inner products
  * out[p][q] = |A_p AND B_q| = <a_s, b_s> (Algorithm 1, second step).
  *

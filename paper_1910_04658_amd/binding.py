@@ -80,6 +80,10 @@ def load():
             L.bs_sketch.argtypes = [p, p, i64, i64, p, i64, i32, p, p, p, p, sz, p]
             L.bs_sketch_parts.argtypes = [ctypes.POINTER(SketchPart), i32, p, i64, i32, p, p, sz, p]
             L.bs_sketch_parts.restype = ctypes.c_int
+            L.bs_sketch_prepare_map.argtypes = [p, i64, i32, p, p, sz, p]
+            L.bs_sketch_prepare_map.restype = ctypes.c_int
+            L.bs_sketch_parts_prepared.argtypes = [ctypes.POINTER(SketchPart), i32, p, i64, i32, p, sz, p, p]
+            L.bs_sketch_parts_prepared.restype = ctypes.c_int
             L.bs_sketch_workspace_size.argtypes = [i64, i32]
             L.bs_sketch_workspace_size.restype = sz
             L.bs_sketch.restype = ctypes.c_int
@@ -238,12 +242,32 @@ def sketch(indptr: torch.Tensor, indices: torch.Tensor, pi: torch.Tensor, N: int
 MAX_PARTS = 4  # BS_SKETCH_MAX_PARTS
 
 
+def prepare_map(pi: torch.Tensor, N: int, err_flag: torch.Tensor | None = None,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """bs_sketch_prepare_map: pi bit-packed once, for sketch_parts(prepared=...)."""
+    _need(pi, "pi", torch.int32, 1)
+    need = sketch_workspace_size(max(pi.numel(), 1), N)
+    if need == 0:
+        raise ValueError("invalid sketch width N=%d" % N)
+    if out is None:
+        out = _workspace(need, pi.device)
+    if err_flag is not None:
+        _need(err_flag, "err_flag", torch.int32)
+    st = load().bs_sketch_prepare_map(_ptr(pi), pi.numel(), int(N), _ptr(err_flag), _ptr(out), out.numel(),
+                                      _stream())
+    _check(st, "bs_sketch_prepare_map")
+    return out
+
+
 def sketch_parts(parts, pi: torch.Tensor, N: int, outs=None, popcounts=None,
-                 err_flag: torch.Tensor | None = None, workspace: torch.Tensor | None | bool = True):
+                 err_flag: torch.Tensor | None = None, workspace: torch.Tensor | None | bool = True,
+                 prepared: torch.Tensor | None = None):
     """bs_sketch_parts: the (indptr, indices) CSR matrices of `parts` (at most
     four) sketched with one map in one launch. outs / popcounts: optional
     lists of preallocated outputs (a None popcounts entry skips that part's
-    counts). Returns [(sketches, popcounts), ...], each as sketch() would."""
+    counts). prepared: a map packed by prepare_map(pi, N), used instead of
+    packing pi on this call (bs_sketch_parts_prepared). Returns
+    [(sketches, popcounts), ...], each as sketch() would."""
     if not 1 <= len(parts) <= MAX_PARTS:
         raise ValueError("1 to %d parts" % MAX_PARTS)
     _need(pi, "pi", torch.int32, 1)
@@ -281,9 +305,15 @@ def sketch_parts(parts, pi: torch.Tensor, N: int, outs=None, popcounts=None,
     elif workspace is False:
         workspace = None
     wsn = workspace.numel() if workspace is not None else 0
-    st = load().bs_sketch_parts(arr, len(parts), _ptr(pi), pi.numel(), int(N), _ptr(err_flag),
-                                _ptr(workspace), wsn, _stream())
-    _check(st, "bs_sketch_parts")
+    if prepared is not None:
+        _need(prepared, "prepared map", torch.uint8, 1)
+        st = load().bs_sketch_parts_prepared(arr, len(parts), _ptr(pi), pi.numel(), int(N), _ptr(prepared),
+                                             prepared.numel(), _ptr(err_flag), _stream())
+        _check(st, "bs_sketch_parts_prepared")
+    else:
+        st = load().bs_sketch_parts(arr, len(parts), _ptr(pi), pi.numel(), int(N), _ptr(err_flag),
+                                    _ptr(workspace), wsn, _stream())
+        _check(st, "bs_sketch_parts")
     return res
 
 

@@ -799,8 +799,11 @@ void split_waves(const bs_sketch_part* parts, int32_t n_parts, int64_t total, in
   for (int i = 0; i < kMaxParts; ++i) wave_off[i + 1] = wave_off[i] + (int32_t)(i < n_parts ? w[i] : 0);
 }
 
+// packed: the workspace already holds pi packed by bs_sketch_prepare_map
+// (no pack launch; pi's values were checked then).
 bs_status sketch_parts_impl(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi, int64_t d, int32_t N,
-                            int32_t* err_flag, void* workspace, size_t workspace_bytes, void* stream) {
+                            int32_t* err_flag, void* workspace, size_t workspace_bytes, void* stream,
+                            bool packed = false) {
   if (n_parts < 1 || n_parts > kMaxParts || d < 1 || d > INT32_MAX || !valid_width(N)) return BS_ERR_ARG;
   if (!parts) return BS_ERR_NULL;
   for (int i = 0; i < n_parts; ++i)
@@ -867,7 +870,7 @@ bs_status sketch_parts_impl(const bs_sketch_part* parts, int32_t n_parts, const 
       split_waves(parts, n_parts, grid * kBigBlockWaves, L.wave_off);
       if (lds > 65536) (void)hipFuncSetAttribute((const void*)sketch_csr_lds_kernel,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      {
+      if (!packed) {
         const int64_t n_groups = (d + 31) / 32;
         ScopedTiming timing("sketch_pack", as_stream(stream));
         hipLaunchKernelGGL(pack_map_kernel, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0,
@@ -914,4 +917,29 @@ extern "C" bs_status bs_sketch_parts(const bs_sketch_part* parts, int32_t n_part
                                      int32_t N, int32_t* err_flag, void* workspace, size_t workspace_bytes,
                                      void* stream) {
   return bs::sketch_parts_impl(parts, n_parts, pi, d, N, err_flag, workspace, workspace_bytes, stream);
+}
+
+extern "C" bs_status bs_sketch_prepare_map(const int32_t* pi, int64_t d, int32_t N, int32_t* err_flag, void* map,
+                                           size_t map_bytes, void* stream) {
+  using namespace bs;
+  if (d < 1 || d > INT32_MAX || !valid_width(N)) return BS_ERR_ARG;
+  if (!pi) return BS_ERR_NULL;
+  if (!map || map_bytes < bs_sketch_workspace_size(d, N) || (reinterpret_cast<uintptr_t>(map) & 15))
+    return BS_ERR_WORKSPACE;
+  bs_status st = check_device();
+  if (st != BS_OK) return st;
+  const int64_t n_groups = (d + 31) / 32;
+  ScopedTiming timing("sketch_pack", as_stream(stream));
+  hipLaunchKernelGGL(pack_map_kernel, dim3((unsigned)((n_groups + 255) / 256)), dim3(256), 0, as_stream(stream), pi,
+                     d, N, map_bits(N), static_cast<uint32_t*>(map), err_flag);
+  return launch_status();
+}
+
+extern "C" bs_status bs_sketch_parts_prepared(const bs_sketch_part* parts, int32_t n_parts, const int32_t* pi,
+                                              int64_t d, int32_t N, const void* map, size_t map_bytes,
+                                              int32_t* err_flag, void* stream) {
+  using namespace bs;
+  if (!map || map_bytes < bs_sketch_workspace_size(d, N) || (reinterpret_cast<uintptr_t>(map) & 15))
+    return (d < 1 || d > INT32_MAX || !valid_width(N)) ? BS_ERR_ARG : BS_ERR_WORKSPACE;
+  return sketch_parts_impl(parts, n_parts, pi, d, N, err_flag, const_cast<void*>(map), map_bytes, stream, true);
 }

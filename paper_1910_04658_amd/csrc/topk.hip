@@ -209,6 +209,12 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.s_qb = (nQ + p.s_nqb - 1) / p.s_nqb;
   if (p.s_qb < 1) p.s_qb = 1;
   p.s_nqb = (nQ + p.s_qb - 1) / p.s_qb;
+  if (p.mma) {  // matrix-core sample pass: blocks of 64 sampled rows x 64 queries
+    p.s_rblocks = (p.S + kWave - 1) / kWave;
+    p.s_qb = kWave;
+    p.s_nqb = (nQ + kWave - 1) / kWave;
+    if (p.s_nqb < 1) p.s_nqb = 1;
+  }
   // LDS of the select kernel: room for 1.25x the expected candidate count
   // (k * nC / S) plus 512, about four standard deviations of the count for
   // k = 100 (a query with more candidates selects in place in its candidate
@@ -1551,6 +1557,79 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   }
 }
 
+// Sample pass on the matrix cores (the widths and batches the matrix-core
+// scan takes): the exact score of every query against each of the S sampled
+// rows (row i * stride) as a selection key in skeys[q][i], from the same
+// FP4 products as the scan. A block takes 64 queries x 64 sampled rows and
+// each of its four waves one 32 x 32 product (query tile wid / 2, row tile
+// wid % 2); the counts become FP32 scores exactly as in the other sample
+// kernels.
+template <int M, int KCT, bool LDS_LUT>
+__device__ __forceinline__ void sample_mma_body(const TopkArgs& a, int64_t bx, int64_t by) {
+  extern __shared__ float lut_s[];
+  const float* lut = a.t32;
+  if (LDS_LUT) {
+    if (a.t32w) {  // small N: every block evaluates T, the first also stores it for the later passes
+      for (int x = threadIdx.x; x <= a.N; x += kThreads) {
+        const float v = (float)t_value(x, a.N);
+        lut_s[x] = v;
+        if (bx == 0 && by == 0) a.t32w[x] = v;
+      }
+    } else {
+      for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    }
+    __syncthreads();
+    lut = lut_s;
+  }
+  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int c = lane % 32, h = lane / 32;
+  const int64_t q0 = by * kWave + 32 * (wid / 2);  // the wave's 32 queries
+  const int64_t i0 = bx * kWave + 32 * (wid % 2);  // the wave's 32 sampled rows
+  if (q0 >= a.nQ || i0 >= a.S) return;  // wave-uniform; no barrier follows
+  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 8;
+  const uint32_t rowb = (uint32_t)W32 * 4u;
+  // operand row c holds query q0 + 16 ((c / 4) % 2) + 4 (c / 8) + c % 4, so
+  // accumulator element e of lane (h, c) is query q0 + 16 h + e (as in the scan)
+  int64_t qr = q0 + 16 * ((c / 4) % 2) + 4 * (c / 8) + c % 4;
+  qr = qr < a.nQ ? qr : a.nQ - 1;
+  const int64_t irow = i0 + c;
+  const int64_t crow = (irow < a.S ? irow : a.S - 1) * a.stride;
+  const char* qp = reinterpret_cast<const char*>(a.Q) + (size_t)qr * rowb + 16u * h;
+  const char* cp = reinterpret_cast<const char*>(a.C) + (size_t)crow * rowb + 16u * h;
+  bs_v16f acc;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+  uint4 av = *reinterpret_cast<const uint4*>(qp), bv = *reinterpret_cast<const uint4*>(cp);
+  constexpr int KU = KCT > 0 && KCT <= 4 ? KCT : 1;
+#pragma unroll KU
+  for (int ch = 0; ch < KC; ++ch) {
+    uint4 an = av, bn = bv;
+    if (ch + 1 < KC) {  // the next chunk loads while this one is multiplied
+      an = *reinterpret_cast<const uint4*>(qp + 32u * (ch + 1));
+      bn = *reinterpret_cast<const uint4*>(cp + 32u * (ch + 1));
+    }
+    const uint32_t aw[4] = {av.x, av.y, av.z, av.w}, bw[4] = {bv.x, bv.y, bv.z, bv.w};
+    acc = mma_class<0>(fp4_class<0>(aw), fp4_class<0>(bw), acc);
+    acc = mma_class<1>(fp4_class<1>(aw), fp4_class<1>(bw), acc);
+    acc = mma_class<2>(fp4_class<2>(aw), fp4_class<2>(bw), acc);
+    acc = mma_class<3>(fp4_class<3>(aw), fp4_class<3>(bw), acc);
+    av = an;
+    bv = bn;
+  }
+  const int32_t xc = a.popC[crow];
+  const float Tc = lut[xc];
+  // lane l holds the weight of query q0 + l % 32; element e of half h reads lane 16 h + e
+  const int64_t ql = q0 + lane % 32 < a.nQ ? q0 + lane % 32 : a.nQ - 1;
+  const int32_t xql = a.popQ[ql];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int32_t xq = __shfl(xql, 16 * h + e);
+    const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc[e]]);
+    const int64_t q = q0 + 16 * h + e;
+    if (irow < a.S && q < a.nQ) a.skeys[(size_t)q * a.S + irow] = score_key<M>(sc);
+  }
+}
+
 // Row-lane scan for batches of at most 64 queries. Each wave owns one slab:
 // a run of 64-row tiles. Lane l holds row (tile + l) in VGPRs; the queries
 // arrive in turn on the scalar unit, so the corpus is read from HBM exactly
@@ -1694,7 +1773,7 @@ __device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, c
 // Slot entries of the query-lane scans are raw (x_c, x_ab, row) and are
 // scored here (RAW); the row-lane scan and the sample pass store final keys.
 template <int M, bool RAW, bool LUT>
-__device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
+__device__ __forceinline__ void select_query(const TopkArgs& a, int64_t q) {
   extern __shared__ uint64_t sm[];  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats
   __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t wsum[kThreads / kWave];
@@ -1735,7 +1814,10 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   if (t == kThreads - 1) total_s = incl;
   __syncthreads();
   if (qovf) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
-    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    if (t == 0) {
+      a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+      __threadfence();  // the entry before this block's ticket (select_body)
+    }
     return;
   }
   const int64_t n = ns + total_s;
@@ -1818,7 +1900,10 @@ __device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
   // score is >= tau, and every row scoring >= tau is a candidate (with
   // kt = k, tau is a lower bound by construction and thr = 0 counts all)
   if (above_s < (uint32_t)a.k) {  // block-uniform: the whole-corpus fallback ranks the query
-    if (t == 0) a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+    if (t == 0) {
+      a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
+      __threadfence();  // the entry before this block's ticket (select_body)
+    }
     return;
   }
   select_and_write<M>(keys, n, q, a, sel, hist, &bprefix, &bneed, &nsel);
@@ -1853,6 +1938,24 @@ __device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int6
     __syncthreads();
     select_and_write<M>(keys, a.nC, q, a, sel, hist, &bprefix, &bneed, &nsel);
   }
+}
+
+// Select of query q, then, in the block that finishes last (a ticket taken
+// after each block's overflow entries are in place), the whole-corpus
+// fallback for every query that overflowed or failed the tau check: with no
+// such query that costs one atomic per block and no extra launch.
+template <int M, bool RAW, bool LUT>
+__device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
+  __shared__ uint32_t last_s;
+  select_query<M, RAW, LUT>(a, q);
+  __syncthreads();
+  // a block that queued its query fenced the entry before this ticket; the
+  // others have nothing to publish
+  if (threadIdx.x == 0) last_s = atomicAdd(&a.ovf[1], 1) == (int32_t)(a.nQ - 1) ? 1u : 0u;
+  __syncthreads();
+  if (!last_s) return;  // block-uniform
+  __threadfence();      // every other block's entries are visible
+  if (__builtin_amdgcn_readfirstlane(*(volatile int32_t*)a.ovf) > 0) fallback_body<M>(a, 0, 1);
 }
 
 // ---- grouped launches ---------------------------------------------------------
@@ -1910,6 +2013,10 @@ __global__ __launch_bounds__(kThreads) void topk_sample_scores_kernel(GroupArgs 
 template <bool ONE, int M, int WS>
 __global__ __launch_bounds__(kThreads) void topk_sample_split_kernel(GroupArgs g) {
   BS_GROUP_LOOP((sample_split_body<M, WS>(a, lb % a.s_rblocks, lb / a.s_rblocks)))
+}
+template <bool ONE, int M, int KCT, bool LDS_LUT>
+__global__ __launch_bounds__(kThreads) void topk_sample_mma_kernel(GroupArgs g) {
+  BS_GROUP_LOOP((sample_mma_body<M, KCT, LDS_LUT>(a, lb % a.s_rblocks, lb / a.s_rblocks)))
 }
 template <bool ONE, int M>
 __global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(GroupArgs g) {
@@ -1970,7 +2077,7 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
       if (a.split) return (a.n_slabs / kSplitWaves) * a.nqb4;
       return a.n_slabs * a.nqb4;
     case kStSelect: return a.nQ;
-    default: return scan ? a.F : 0;
+    default: return 0;  // the fallback runs in the select's last block
   }
 }
 
@@ -1978,11 +2085,15 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
 size_t stage_lds(const TopkArgs& a, int st) {
   const bool lds_lut = a.N <= 16384;
   switch (st) {
-    case kStSample: return (lds_lut || a.split) ? (size_t)(a.N + 1) * 4 : 0;
+    case kStSample: return (lds_lut || (a.split && !a.mma)) ? (size_t)(a.N + 1) * 4 : 0;
     case kStSampleSelect: return (size_t)a.S * 4;
     case kStBound: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
     case kStScan: return a.rows ? (size_t)(a.N + 1) * 4 : 0;
-    case kStSelect: return (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8 + (select_lut(a) ? (size_t)(a.N + 1) * 4 : 0);
+    case kStSelect: {  // also room for the fallback (selected keys, then the query's words)
+      const size_t sel = (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8 + (select_lut(a) ? (size_t)(a.N + 1) * 4 : 0);
+      const size_t fb = (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
+      return sel > fb ? sel : fb;
+    }
     default: return (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
   }
 }
@@ -1995,6 +2106,17 @@ const void* stage_kernel(const TopkArgs& a, int st) {
   const bool pow2 = (W32 & (W32 - 1)) == 0;
   switch (st) {
     case kStSample:
+      if (a.mma) {
+        if (!lds_lut) return (const void*)topk_sample_mma_kernel<ONE, M, 0, false>;
+        switch (W32 / 8) {  // 256-bit chunks per row
+          case 1: return (const void*)topk_sample_mma_kernel<ONE, M, 1, true>;
+          case 2: return (const void*)topk_sample_mma_kernel<ONE, M, 2, true>;
+          case 4: return (const void*)topk_sample_mma_kernel<ONE, M, 4, true>;
+          case 8: return (const void*)topk_sample_mma_kernel<ONE, M, 8, true>;
+          case 16: return (const void*)topk_sample_mma_kernel<ONE, M, 16, true>;
+          default: return (const void*)topk_sample_mma_kernel<ONE, M, 0, true>;
+        }
+      }
       if (a.split)
         return W32 == 256 ? (const void*)topk_sample_split_kernel<ONE, M, 64>
                           : (const void*)topk_sample_split_kernel<ONE, M, 128>;

@@ -67,6 +67,27 @@ def test_sketch_rejects_bad_arguments(lib):
         assert s(FAKE, FAKE, 1, 1, FAKE, 10, N, FAKE, None, None, None, 0, None) == 2
 
 
+def test_prepared_map_rejects_bad_arguments(lib):
+    from paper_1910_04658_amd.binding import SketchPart
+    need = lib.bs_sketch_workspace_size(10, 64)
+    assert need > 0
+    p = lib.bs_sketch_prepare_map
+    assert p(None, 10, 64, None, FAKE, need, None) == 1
+    assert p(FAKE, 0, 64, None, FAKE, need, None) == 2
+    assert p(FAKE, 10, 96, None, FAKE, need, None) == 2
+    assert p(FAKE, 10, 64, None, None, need, None) == 3
+    assert p(FAKE, 10, 64, None, FAKE, need - 1, None) == 3
+    assert p(FAKE, 10, 64, None, P(0x1001), need, None) == 3
+    good = SketchPart(FAKE, FAKE, 1, 1, FAKE, None)
+    arr = (SketchPart * 1)(good)
+    s = lib.bs_sketch_parts_prepared
+    assert s(arr, 1, FAKE, 10, 64, None, need, None, None) == 3
+    assert s(arr, 1, FAKE, 10, 64, FAKE, need - 1, None, None) == 3
+    assert s(arr, 1, FAKE, 10, 100, FAKE, need, None, None) == 2
+    assert s(arr, 0, FAKE, 10, 64, FAKE, need, None, None) == 2
+    assert s(arr, 1, None, 10, 64, FAKE, need, None, None) == 1
+
+
 def test_pairs_reject_bad_arguments(lib):
     assert lib.bs_and_popcount(None, 1, FAKE, 1, 64, FAKE, None) == 1
     assert lib.bs_and_popcount(FAKE, -1, FAKE, 1, 64, FAKE, None) == 2

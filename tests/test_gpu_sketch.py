@@ -174,3 +174,42 @@ def test_parts_error_flag(dev):
                     pi, 1024, err_flag=flag)
     torch.cuda.synchronize()
     assert int(flag.item()) & bs.FLAG_INDEX
+
+
+@pytest.mark.parametrize("N", [256, 1024, 4096, 16384])
+def test_prepared_map_equals_per_call_packing(N, dev):
+    """A map packed once by bs_sketch_prepare_map and reused by
+    bs_sketch_parts_prepared gives exactly the sketches and popcounts of
+    bs_sketch_parts (which packs the map on every call), over two calls in a
+    row on different inputs (d = 100,000); at N = 16384 the packed map
+    (175 KB) does not fit in LDS and both take the gathered path."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    pi_np = datagen.random_map(100_000, N, 41)
+    pi = to_dev(pi_np, dev)
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    packed = bs.prepare_map(pi, N, err_flag=flag)
+    for seed in (42, 43):
+        a = datagen.lognormal_corpus(5000, d=100_000, seed=seed)
+        b = datagen.lognormal_corpus(300, d=100_000, seed=seed + 100)
+        parts = [(to_dev(a.indptr, dev), to_dev(a.indices, dev)), (to_dev(b.indptr, dev), to_dev(b.indices, dev))]
+        got = bs.sketch_parts(parts, pi, N, err_flag=flag, prepared=packed)
+        want = bs.sketch_parts(parts, pi, N, err_flag=flag)
+        torch.cuda.synchronize()
+        for (w, p), (w1, p1) in zip(got, want):
+            assert torch.equal(w, w1) and torch.equal(p, p1)
+    assert int(flag.item()) == 0
+    ow, op = oracle.sketch(b.indptr, b.indices, b.d, pi_np, N)
+    assert np.array_equal(words_np(got[1][0]), ow) and np.array_equal(got[1][1].cpu().numpy(), op)
+
+
+def test_prepare_map_flags_bad_values(dev):
+    """Map values outside [0, N) are reported when the map is prepared."""
+    import torch
+    from paper_1910_04658_amd import binding as bs
+    pi_np = datagen.random_map(5000, 1024, 44)
+    pi_np[123] = 1024
+    flag = torch.zeros(1, dtype=torch.int32, device=dev)
+    bs.prepare_map(to_dev(pi_np, dev), 1024, err_flag=flag)
+    torch.cuda.synchronize()
+    assert int(flag.item()) & bs.FLAG_MAP
