@@ -207,8 +207,8 @@ def timed(step, steps, warmup, graph=False):
     bs.timing_enable(False)
     bad = bs.timing_collect()
     kt = {}
-    for name in ["sketch_pack", "sketch_csr", "topk_prep", "topk_sample", "topk_bound", "topk_scan", "topk_select",
-                 "topk_fallback"]:
+    for name in ["sketch_pack", "sketch_csr", "topk_prep", "topk_sample", "topk_sample_select", "topk_bound",
+                 "topk_scan", "topk_select"]:
         ms, n = bs.timing_get(name)
         if n:
             kt[name] = {"avg_ms": ms / n, "launches": n, "per_step": n / n_timed}

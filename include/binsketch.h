@@ -405,8 +405,8 @@ bs_status bs_mlp_to_bf16(const float* master, uint16_t* w, void* stream);
  * stream (so it must not be used under graph capture). bs_timing_collect
  * waits for the recorded events and adds each kernel's elapsed time to a
  * per-name total ("sketch_csr", "pair_and_popcount", "pair_estimate",
- * "topk_prep", "topk_sample", "topk_bound", "topk_scan", "topk_select",
- * "topk_fallback", "sketch_pack");
+ * "topk_prep", "topk_sample", "topk_sample_select", "topk_bound",
+ * "topk_scan", "topk_select", "sketch_pack");
  * it returns the number of event pairs that could not be read.
  * bs_timing_get returns 1 and the total milliseconds and launch count for a
  * name, or 0 if the name has not been timed. Process-wide, thread-safe.

@@ -6,7 +6,7 @@
 // covering every problem in the batch: a flag-clearing kernel, one launch
 // that packs every map to 16-bit targets, ONE sketch launch for every corpus
 // and query matrix, one LUT launch per distinct width,
-// then the top-k stages (sample, threshold table, scan, select, fallback),
+// then the top-k stages (sample, sample select, threshold table, scan, select),
 // one launch per stage and kernel variant (a variant is fixed by the width and
 // the scan tile shape). The grids are persistent (at most what fits the
 // device at once) and walk a table of virtual blocks that spans all

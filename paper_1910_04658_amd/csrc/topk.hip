@@ -7,7 +7,8 @@
 // are returned ordered by (score, then smaller index). The paper ranks by a
 // similarity threshold (Section 4.2); a fixed k is the serving form of it.
 //
-// Selection without a global sort, in three launches plus a rare fallback:
+// Selection without a global sort, in three passes (five launches; the
+// fallback runs inside the third):
 //  1. sample: per query (one block), score a strided sample of S corpus rows,
 //     find the kt-th best score tau among them by an LDS radix select, append
 //     the sample rows scoring >= tau to the query's candidate list, and store
@@ -32,9 +33,11 @@
 //     k candidates scoring >= tau, the true k-th best score is >= tau, and
 //     every row scoring >= tau is a candidate, so the selection is exact.
 //  4. fallback: a query that fails that check, or has more survivors in one
-//     slab than its slot range holds (e.g. massive exact ties), is recomputed
-//     over the whole corpus by a few blocks and selected the same way. Results
-//     never depend on which path ran.
+//     slab than its slot range holds (e.g. massive exact ties), is ranked by
+//     its select block over the whole corpus instead, streaming the rows
+//     through an LDS buffer that is cut back to its k best whenever it fills
+//     (no extra launch, no corpus-sized scratch). Results never depend on
+//     which path ran.
 #include <float.h>
 #include <string.h>
 
@@ -64,15 +67,14 @@ constexpr int kRowsMaxQ = 64;        // largest batch of the row-lane scan
 constexpr int kSplitWaves = 4;       // waves sharing one 64-query group in the word-split scan
 constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, about
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
-constexpr int kFallbackBlocks = 16;
+constexpr int kFbRowsPerThread = 2; // corpus rows per thread per step of the whole-corpus fallback
 constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
-#ifndef BS_EXP_MMA_WAVES
-#define BS_EXP_MMA_WAVES 16384
-#endif
-constexpr int kMmaWaves = BS_EXP_MMA_WAVES;     // waves of the matrix-core scan grid, about
+constexpr int kMmaWaves = 16384;      // waves of the matrix-core scan grid, about
 constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
 constexpr int kMmaQCap = 256;         // survivor queue entries per wave of the matrix-core scan
 constexpr int kMmaHoldChunks = 2;     // the matrix-core scan holds a group's query words in registers up to this many chunks
+
+__host__ __device__ constexpr int64_t round_up64(int64_t x) { return (x + 63) / 64 * 64; }
 
 struct QConst {  // per-query constants written by the sample pass
   float tau;     // (a lower bound on) the kt-th best sample score
@@ -84,7 +86,7 @@ struct QConst {  // per-query constants written by the sample pass
 };
 
 struct Plan {
-  int64_t S, stride, F;
+  int64_t S, stride;
   int64_t kt;  // rank of tau in the sample
   int64_t qpl, ngrp, nqb4, n_slabs, slab, scap, kmax;  // scan geometry
   int64_t s_rblocks, s_nqb, s_qb;                     // sample-score grid
@@ -94,7 +96,7 @@ struct Plan {
   bool sel_lut;                                       // select keeps T in LDS
   int64_t lds_keys;                                   // select: candidate keys held in LDS
   size_t off_t32, off_popq, off_popc, off_qc, off_cnts, off_cands, off_scnt, off_qovf,
-      off_scratch, off_mtab, off_ovf, off_skeys, total;
+      off_mtab, off_skeys, total;
 };
 
 // Sample size: 2,048 rows, growing as nC/256 up to 15,360 for large corpora
@@ -225,15 +227,11 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
     p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
     int64_t kpad = 1;
     while (kpad < k) kpad <<= 1;
-    const int64_t lut_bytes = (int64_t)(N + 1) * 4;
+    const int64_t lut_bytes = round_up64(N + 1) * 4;
     p.sel_lut = !p.rows && N <= 2048 && (61440 - kpad * 8 - lut_bytes) / 8 >= 1024;  // (larger T costs occupancy)
     const int64_t cap = (61440 - kpad * 8 - (p.sel_lut ? lut_bytes : 0)) / 8;
     if (p.lds_keys > cap) p.lds_keys = cap;
   }
-  // fallback blocks: at most 16, and at most 256 MB of whole-corpus key scratch
-  int64_t F = (INT64_C(256) << 20) / (8 * nC);
-  F = F < 1 ? 1 : (F > kFallbackBlocks ? kFallbackBlocks : F);
-  p.F = nQ < F ? nQ : F;
   const size_t nQs = (size_t)nQ;
   size_t o = 0;
   auto take = [&o](size_t bytes) {
@@ -250,9 +248,7 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   p.off_scnt = take(nQs * (size_t)p.n_slabs * 4);
   p.off_qovf = take(nQs * 4);
 
-  p.off_scratch = take((size_t)p.F * (size_t)nC * 8);
   p.off_mtab = take((size_t)(N + 2) * (size_t)((nQ + 63) / 64 * 64) * 2);  // rows 0..N, then N + 1: all 65535
-  p.off_ovf = take((nQs + 2) * 4);
   p.off_skeys = take(nQs * (size_t)p.S * 4);
   p.total = o;
   return p;
@@ -278,14 +274,52 @@ __device__ __forceinline__ uint64_t raw_entry(uint32_t xab, int32_t xc, int64_t 
   return (hi << 32) | (uint32_t)row;
 }
 
+// Inclusive scan over the 64 lanes of a wave (every lane active) by DPP row
+// shifts within each 16-lane row, then row broadcasts across rows: six VALU
+// steps with no LDS round trip (a lane with no source adds 0).
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15 into rows 1, 3
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+// Largest / smallest / total of v over a wave (every lane active), in every
+// lane: the same DPP steps as the scan (a lane with no source takes the
+// operation's identity), then lane 63's value. Reducing within the wave first
+// keeps same-address LDS atomics, which serialize, to one per wave.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#define BS_DPP_MAX(ctrl, rows) \
+  { const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rows, 0xF, false); v = o > v ? o : v; }
+  BS_DPP_MAX(0x111, 0xF) BS_DPP_MAX(0x112, 0xF) BS_DPP_MAX(0x114, 0xF) BS_DPP_MAX(0x118, 0xF)
+  BS_DPP_MAX(0x142, 0xA) BS_DPP_MAX(0x143, 0xC)
+#undef BS_DPP_MAX
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, kWave - 1);
+}
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) { return ~wave_max_u32(~v); }
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(v), kWave - 1);
+}
+
+// Appends to a block-shared list: each lane with `take` gets a distinct slot
+// from *count, with one LDS atomic per wave (a ballot and a prefix count
+// number the wave's lanes). Call with the wave's lanes active from lane 0 up
+// (every lane that takes part has all lower lanes active).
+__device__ __forceinline__ uint32_t wave_append(bool take, uint32_t* count) {
+  const uint64_t m = __ballot(take);
+  const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+  uint32_t base = 0;
+  if (m && threadIdx.x % kWave == 0) base = atomicAdd(count, (uint32_t)__popcll(m));
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + before;
+}
+
 // Block-wide (256 threads) inclusive scan over thread order.
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t v, uint32_t* wsum) {
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t t = __shfl_up(v, off);
-    if (lane >= off) v += t;
-  }
+  v = wave_incl_scan(v);
   if (lane == kWave - 1) wsum[wid] = v;
   __syncthreads();
   uint32_t add = 0;
@@ -309,9 +343,29 @@ __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* wsum) {
   return m;
 }
 
+// Block-wide copy of n >= 1 32-bit words from global memory to LDS by
+// direct-to-LDS loads: no registers, and one wait at the end, so the copy
+// shares its round trip with the loads issued before it (the caller's barrier
+// publishes the words). Lanes past n re-read word n - 1 into the padding:
+// dst has room for n rounded up to 64 words.
+__device__ __forceinline__ void copy_words_to_lds(uint32_t* dst, const uint32_t* src, int64_t n) {
+  const int lane = threadIdx.x % kWave;
+  for (int64_t j = threadIdx.x / kWave; j * kWave < n; j += kThreads / kWave) {
+    const int64_t i = j * kWave + lane;
+    __builtin_amdgcn_global_load_lds(src + (i < n ? i : n - 1), dst + j * kWave, 4, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
+struct KeyIdentity {
+  template <typename K>
+  __device__ K operator()(K key) const { return key; }
+};
+
 // MSB-first radix select of the k largest of n keys (1 <= k <= n), in
 // digits of up to 8 bits from bit hb - 1 down to bit min_bit; every key has
-// the bits pmask0 (those at and above hb) equal to prefix0. On return the k
+// the bits pmask0 (those at and above hb) equal to prefix0. The keys are
+// taken through xf (an order-preserving map; the result is in its terms). On return the k
 // largest are exactly the keys with (key & *pmask_out) >= prefix (the return
 // value) when min_bit is 0: either every digit was resolved (prefix is then
 // the k-th largest key itself) or, with `early`, the bin holding the k-th
@@ -320,10 +374,10 @@ __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* wsum) {
 // key, a lower bound on it. `keys` may be in LDS or global memory; `hist`
 // holds 2 x 256 counters used in turn (the wave that scans one clears the
 // other), so a pass costs two block barriers. Block-wide call.
-template <typename K>
+template <typename K, typename Xf = KeyIdentity>
 __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, K* bcast_prefix,
                               int64_t* bcast_need, K* pmask_out, bool early, int hb, K prefix0, K pmask0,
-                              int min_bit) {
+                              int min_bit, Xf xf = Xf()) {
   __shared__ int done;
   const int t = threadIdx.x;
   K prefix = prefix0, pmask = pmask0;
@@ -338,7 +392,7 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
     const uint32_t dmask = (1u << (hb - lo)) - 1u;
     uint32_t* h = hist + buf * kThreads;
     for (int64_t i = t; i < n; i += kThreads) {
-      const K key = keys[i];
+      const K key = xf(keys[i]);
       if ((key & pmask) == prefix) atomicAdd(&h[(uint32_t)(key >> lo) & dmask], 1u);
     }
     __syncthreads();
@@ -349,12 +403,7 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
         c[j] = h[255 - 4 * t - j];
         sum += c[j];
       }
-      uint32_t incl = sum;
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t o = __shfl_up(incl, off);
-        if (t >= off) incl += o;
-      }
+      const uint32_t incl = wave_incl_scan(sum);
       uint32_t e = incl - sum;  // keys in the bins above this lane's
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -413,55 +462,6 @@ __device__ void block_key_range(const K* keys, int64_t n, uint64_t* lo_out, uint
 }
 
 
-// Descending bitonic sort of n (power of two, <= 2 * kThreads * 8) keys in LDS.
-__device__ void bitonic_sort_desc(uint64_t* v, int n) {
-  if (n <= 2 * kWave) {
-    // wave 0 sorts in registers: element i in lane i % 64, register i / 64
-    // (missing elements are 0, below every key); partners across lanes are
-    // exchanged with cross-lane swaps, no LDS traffic and no barriers
-    if (threadIdx.x < kWave) {
-      const int l = threadIdx.x;
-      uint64_t a = l < n ? v[l] : 0, b = l + kWave < n ? v[l + kWave] : 0;
-#pragma unroll
-      for (int size = 2; size <= 2 * kWave; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-          if (stride == kWave) {  // partners in one lane; size 128 sorts descending
-            const uint64_t hi = a > b ? a : b, lo = a > b ? b : a;
-            a = hi;
-            b = lo;
-          } else {
-            const uint64_t pa = __shfl_xor(a, stride), pb = __shfl_xor(b, stride);
-            const bool lower = (l & stride) == 0;  // this element has the smaller index of its pair
-            const bool da = (l & size) == 0, db = ((l + kWave) & size) == 0;  // descending runs
-            a = (lower == da) ? (a > pa ? a : pa) : (a < pa ? a : pa);
-            b = (lower == db) ? (b > pb ? b : pb) : (b < pb ? b : pb);
-          }
-        }
-      }
-      if (l < n) v[l] = a;
-      if (l + kWave < n) v[l + kWave] = b;
-    }
-    __syncthreads();
-    return;
-  }
-  for (int size = 2; size <= n; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int t = threadIdx.x; t < n / 2; t += kThreads) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool desc = ((lo & size) == 0);
-        const uint64_t a = v[lo], b = v[hi];
-        if (desc ? (a < b) : (a > b)) {
-          v[lo] = b;
-          v[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
 struct TopkArgs {
   const uint64_t* __restrict__ Q;  // [nQ][W64]
   const uint64_t* __restrict__ C;  // [nC][W64]
@@ -477,20 +477,18 @@ struct TopkArgs {
                                    // scans); compacted into keys by the select
   int32_t* __restrict__ scnt;      // [nQ][n_slabs] scan candidates per slab
   int32_t* __restrict__ qovf;      // [nQ] 1 when a slab's slots overflowed
-  uint64_t* __restrict__ scratch;  // [F][nC]
   uint16_t* __restrict__ mtab;     // [N+2][nQp] pair-count thresholds (row N+1: 65535)
-  int32_t* __restrict__ ovf;       // [2 + nQ]: count, key buffers taken, then the overflowed queries
   uint32_t* __restrict__ skeys;    // [nQ][S] sample keys
   int32_t* __restrict__ out_idx;   // [nQ][k]
   float* __restrict__ out_score;   // [nQ][k] or null
   int64_t nQ, nQp, nC, S, stride, n_slabs, slab, nqb4, scap, kmax, lds_keys;
   int64_t s_rblocks, s_nqb, s_qb;  // sample-score grid: row blocks x query blocks of s_qb queries
-  int64_t F;                       // fallback blocks
   int32_t N, W32, k, kpad;
   int32_t kt;                      // rank of tau in the sample (<= k)
   int32_t qpl, rows, split;        // scan variant: queries per lane, row-lane scan, word-split scan
   int32_t mma;                     // matrix-core scan (split then only selects the sample kernel)
   int32_t sel_lut;                 // the select keeps T in LDS
+  int32_t sel_per;                 // slabs per thread in the select (4, or 8 past 1024 slabs)
 };
 
 // Member-wise copy through the constant address space, so that the fields of
@@ -510,9 +508,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.cands = c->cands;
   a.scnt = c->scnt;
   a.qovf = c->qovf;
-  a.scratch = c->scratch;
   a.mtab = c->mtab;
-  a.ovf = c->ovf;
   a.skeys = c->skeys;
   a.out_idx = c->out_idx;
   a.out_score = c->out_score;
@@ -530,7 +526,6 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.s_rblocks = c->s_rblocks;
   a.s_nqb = c->s_nqb;
   a.s_qb = c->s_qb;
-  a.F = c->F;
   a.N = c->N;
   a.W32 = c->W32;
   a.k = c->k;
@@ -541,6 +536,7 @@ __device__ __forceinline__ TopkArgs load_args(const TopkArgs* p) {
   a.split = c->split;
   a.mma = c->mma;
   a.sel_lut = c->sel_lut;
+  a.sel_per = c->sel_per;
   return a;
 }
 
@@ -610,7 +606,7 @@ __device__ __forceinline__ void sample_scores_body(const TopkArgs& a, int64_t bx
         if (bx == 0 && by == 0) a.t32w[x] = v;
       }
     } else {
-      for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+      copy_words_to_lds(reinterpret_cast<uint32_t*>(lut_s), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
     }
     __syncthreads();
     lut = lut_s;
@@ -716,7 +712,7 @@ template <int M, int WS>
 __device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut[];  // T[0..N] (N <= 16384)
   __shared__ uint32_t part[kSplitRows][kSplitWaves][kWave];
-  for (int x = threadIdx.x; x <= a.N; x += kThreads) lut[x] = a.t32[x];
+  copy_words_to_lds(reinterpret_cast<uint32_t*>(lut), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
   __syncthreads();
   constexpr int PS = 32;
   constexpr int P = WS / PS;
@@ -773,39 +769,50 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
   __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t bprefix;
   __shared__ int64_t bneed;
-  __shared__ uint32_t nsel;
-  const uint32_t* src = a.skeys + (size_t)q * a.S;
-  for (int64_t i = threadIdx.x; i < a.S; i += kThreads) keys[i] = src[i];
-  if (threadIdx.x == 0) nsel = 0;
-  if (q == 0 && threadIdx.x == 0) {
-    a.ovf[0] = 0;
-    a.ovf[1] = 0;
+  __shared__ uint32_t nsel, kmin_s, kmax_s;
+  const int32_t xq = a.popQ[q];  // (arrives with the keys)
+  copy_words_to_lds(keys, a.skeys + (size_t)q * a.S, a.S);
+  if (threadIdx.x == 0) {
+    nsel = 0;
+    kmin_s = ~0u;
+    kmax_s = 0;
   }
   __syncthreads();
   // tau: the k-th best sample key resolved to the 16 bits below the highest
   // bit where the keys differ. The lower edge of its bin is a lower bound on
   // it, which is all the filter needs: every row scoring at least tau becomes
   // a candidate, and the final selection is exact.
-  uint64_t klo, khi;
-  block_key_range(keys, a.S, &klo, &khi);
-  const uint32_t diff = (uint32_t)(klo ^ khi);
+  uint32_t mn = ~0u, mx = 0;
+  for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
+    const uint32_t key = keys[i];
+    mn = key < mn ? key : mn;
+    mx = key > mx ? key : mx;
+  }
+  mn = wave_min_u32(mn);
+  mx = wave_max_u32(mx);
+  if (threadIdx.x % kWave == 0) {
+    atomicMin(&kmin_s, mn);
+    atomicMax(&kmax_s, mx);
+  }
+  __syncthreads();
+  const uint32_t klo = kmin_s, khi = kmax_s;
+  const float Tq = a.t32[xq];  // (used at the end: its load overlaps the selection)
+  const uint32_t diff = klo ^ khi;
   const int hb = diff ? 32 - __clz((int)diff) : 0;
   const uint32_t pmask0 = hb >= 32 ? 0u : ~((1u << hb) - 1u);
   const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.kt, hist, &bprefix, &bneed, nullptr, true, hb,
                                                       (uint32_t)khi & pmask0, pmask0, hb > 16 ? hb - 16 : 0);
   uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
-    if (keys[i] >= tau_key) {
-      const uint32_t slot = atomicAdd(&nsel, 1u);
-      cq[slot] = ((uint64_t)keys[i] << 32) | (uint32_t)~(uint32_t)(i * a.stride);
-    }
+    const bool win = keys[i] >= tau_key;
+    const uint32_t slot = wave_append(win, &nsel);
+    if (win) cq[slot] = ((uint64_t)keys[i] << 32) | (uint32_t)~(uint32_t)(i * a.stride);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const int32_t xq = a.popQ[q];
     a.cnts[q] = (int32_t)nsel;
     a.qovf[q] = 0;
-    QConst c = make_qconst<M>(key_score<M>(tau_key), a.t32[xq], xq);
+    QConst c = make_qconst<M>(key_score<M>(tau_key), Tq, xq);
     c.tau_key = tau_key;
     a.qc[q] = c;
   }
@@ -824,7 +831,7 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
   extern __shared__ float lut_s[];
   const float* lut = a.t32;
   if (LDS_LUT) {
-    for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+    copy_words_to_lds(reinterpret_cast<uint32_t*>(lut_s), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
     __syncthreads();
     lut = lut_s;
   }
@@ -1576,7 +1583,7 @@ __device__ __forceinline__ void sample_mma_body(const TopkArgs& a, int64_t bx, i
         if (bx == 0 && by == 0) a.t32w[x] = v;
       }
     } else {
-      for (int x = threadIdx.x; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+      copy_words_to_lds(reinterpret_cast<uint32_t*>(lut_s), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
     }
     __syncthreads();
     lut = lut_s;
@@ -1641,7 +1648,7 @@ __device__ __forceinline__ void sample_mma_body(const TopkArgs& a, int64_t bx, i
 template <int M, int W32T>
 __device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
   extern __shared__ float lut[];  // T[0..N]
-  for (int x = threadIdx.x; x <= a.N; x += kThreads) lut[x] = a.t32[x];
+  copy_words_to_lds(reinterpret_cast<uint32_t*>(lut), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
   __syncthreads();
   constexpr int PS = W32T < 32 ? W32T : 32;  // query words per scalar piece
   const int lane = threadIdx.x % kWave;
@@ -1722,38 +1729,148 @@ __device__ __forceinline__ void scan_rows_body(const TopkArgs& a, int64_t bid) {
 
 // ---- pass 3: exact selection of each query's candidates -----------------------
 
-template <int M>
-__device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a,
-                                 uint64_t* sel, uint32_t* hist, uint64_t* bprefix, int64_t* bneed,
-                                 uint32_t* nsel) {
-  // the highest digit in which the keys differ: the bits above it are common
-  // to every key, so the radix select starts there
-  uint64_t lo, hi;
-  block_key_range(keys, n, &lo, &hi);
-  const uint64_t diff = lo ^ hi;
-  const int hb = diff ? 64 - __clzll((long long)diff) : 0;
+// The k best of n unique keys (1 <= k <= n) into sel[0..k), unordered. The
+// radix select runs on xf(key) (an order-preserving map), whose bits at and
+// above hb equal those of prefix0 for every key. Returns the radix select's
+// prefix: the winners are exactly the keys with (xf(key) & *pmask_out) >=
+// prefix. Block-wide; ends with a barrier.
+template <typename Xf = KeyIdentity>
+__device__ uint64_t select_top(const uint64_t* keys, int64_t n, int64_t k, int hb, uint64_t prefix0, uint64_t* sel,
+                               uint32_t* hist, uint64_t* bprefix, int64_t* bneed, uint32_t* nsel,
+                               uint64_t* pmask_out, Xf xf = Xf()) {
   const uint64_t pmask0 = hb >= 64 ? 0 : ~((((uint64_t)1) << hb) - 1);
   uint64_t pmask = 0;
-  const uint64_t kth =
-      radix_select_kth<uint64_t>(keys, n, a.k, hist, bprefix, bneed, &pmask, true, hb, hi & pmask0, pmask0, 0);
+  const uint64_t kth = radix_select_kth<uint64_t, Xf>(keys, n, k, hist, bprefix, bneed, &pmask, true, hb,
+                                                      prefix0 & pmask0, pmask0, 0, xf);
   if (threadIdx.x == 0) *nsel = 0;
-  for (int t = threadIdx.x; t < a.kpad; t += kThreads) sel[t] = 0;
   __syncthreads();
   for (int64_t i = threadIdx.x; i < n; i += kThreads) {
     const uint64_t key = keys[i];
-    if ((key & pmask) >= kth) {  // exactly k keys: the keys are unique
-      const uint32_t slot = atomicAdd(nsel, 1u);
-      if (slot < (uint32_t)a.kpad) sel[slot] = key;
+    const bool win = (xf(key) & pmask) >= kth;  // exactly k keys: the keys are unique
+    const uint32_t slot = wave_append(win, nsel);
+    if (win) sel[slot] = key;
+  }
+  __syncthreads();
+  *pmask_out = pmask;
+  return kth;
+}
+
+// Radix start for keys spanning [lo, hi]: the highest bit in which they can
+// differ (the bits above are common to all).
+__device__ __forceinline__ int range_top_bit(uint64_t lo, uint64_t hi) {
+  const uint64_t diff = lo ^ hi;
+  return diff ? 64 - __clzll((long long)diff) : 0;
+}
+
+// A candidate key (score key << 32 | ~row) as a shorter key of the same
+// order: (score key - the smallest score key) << b, then (2^b - 1 - row),
+// with 2^b > every row. Ties of the score are broken by the row in the low b
+// bits, so the radix select resolves no bits that no key uses.
+struct KeyCompress {
+  uint32_t base;  // smallest score key
+  int b;          // row bits
+  uint32_t mask;  // 2^b - 1
+  __device__ uint64_t operator()(uint64_t key) const {
+    return ((uint64_t)((uint32_t)(key >> 32) - base) << b) | (uint64_t)(mask - ~(uint32_t)key);
+  }
+};
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// The k best of n unique keys, written best first as row indices (and
+// scores) of query q. Each winner's place is the number of winners above
+// it: a wave takes 64 winners, one per lane, and compares each with every
+// winner, 64 at a time from registers (readlane), so the ordering costs
+// about k^2 / 16 wave instructions and no LDS traffic.
+template <int M, typename Xf = KeyIdentity>
+__device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a, int hb,
+                                 uint64_t prefix0, uint64_t* sel, uint32_t* hist, uint64_t* bprefix, int64_t* bneed,
+                                 uint32_t* nsel, Xf xf = Xf()) {
+  uint64_t pmask;
+  select_top<Xf>(keys, n, a.k, hb, prefix0, sel, hist, bprefix, bneed, nsel, &pmask, xf);
+  const int lane = threadIdx.x % kWave;
+  for (int wb = (threadIdx.x / kWave) * kWave; wb < a.k; wb += kThreads) {  // wave-uniform
+    const int w = wb + lane;
+    const uint64_t kw = w < a.k ? sel[w] : 0;
+    uint32_t r = 0;
+    for (int cb = 0; cb < a.k; cb += kWave) {
+      const uint64_t kc = cb + lane < a.k ? sel[cb + lane] : 0;  // 0 is below every key
+#pragma unroll
+      for (int j = 0; j < kWave; ++j) r += readlane64(kc, j) > kw ? 1u : 0u;
+    }
+    if (w < a.k) {
+      a.out_idx[q * a.k + r] = (int32_t)(~(uint32_t)kw);
+      if (a.out_score) a.out_score[q * a.k + r] = key_score<M>((uint32_t)(kw >> 32));
     }
   }
   __syncthreads();
-  bitonic_sort_desc(sel, a.kpad);
-  for (int t = threadIdx.x; t < a.k; t += kThreads) {
-    const uint64_t key = sel[t];
-    a.out_idx[q * a.k + t] = (int32_t)(~(uint32_t)key);
-    if (a.out_score) a.out_score[q * a.k + t] = key_score<M>((uint32_t)(key >> 32));
-  }
+}
+
+// Whole-corpus selection of query q by its own block, for a query whose
+// candidate list cannot be trusted (a slab had more survivors than slots, or
+// fewer than k candidates reach tau). Every corpus row is scored; the keys
+// that can still be among the k best wait in an LDS buffer of
+// kpad + kFbRowsPerThread * 256 keys, which is cut back to its k best
+// whenever the next step's rows might not fit. After a cut only keys >= the
+// cut's prefix can still be among the k best (k keys already are), so each cut
+// raises the bar for the rows after it. Keys are unique (every key is
+// nonzero), so the result equals one selection over all nC keys.
+// LDS: sel[kpad], the buffer, the query's words.
+template <int M>
+__device__ void fallback_query(const TopkArgs& a, int64_t q, uint64_t* sm, uint32_t* hist, uint64_t* bprefix,
+                               int64_t* bneed, uint32_t* nsel, uint32_t* wsum, uint32_t* total_s) {
+  constexpr int R = kFbRowsPerThread;
+  const int t = threadIdx.x;
+  const int W64 = a.W32 / 2;
+  uint64_t* sel = sm;
+  uint64_t* buf = sm + a.kpad;
+  const int64_t cap = (int64_t)a.kpad + (int64_t)R * kThreads;
+  uint64_t* qw = buf + cap;
+  const uint64_t* qrow = a.Q + (size_t)q * W64;
+  for (int w = t; w < W64; w += kThreads) qw[w] = qrow[w];
+  const int32_t xq = a.popQ[q];
+  const float Tq = a.t32[xq];
   __syncthreads();
+  int64_t cur = 0;   // keys in the buffer (block-uniform)
+  uint64_t thr = 0;  // keys below thr cannot be among the k best
+  for (int64_t base = 0; base < a.nC; base += (int64_t)R * kThreads) {
+    if (cur + (int64_t)R * kThreads > cap) {  // block-uniform: cut the buffer back to its k best
+      uint64_t pmask, lo, hi;
+      block_key_range(buf, cur, &lo, &hi);
+      thr = select_top(buf, cur, a.k, range_top_bit(lo, hi), hi, sel, hist, bprefix, bneed, nsel, &pmask);
+      for (int i = t; i < a.k; i += kThreads) buf[i] = sel[i];
+      cur = a.k;
+      __syncthreads();
+    }
+    uint64_t key[R];
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int64_t i = base + (int64_t)j * kThreads + t;
+      key[j] = 0;
+      if (i < a.nC) {
+        const int32_t xab = and_popcount_row(qw, a.C + (size_t)i * W64, W64);
+        const int32_t xc = a.popC[i];
+        key[j] = make_key<M>(score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]), (uint32_t)i);
+      }
+      c += (key[j] != 0 && key[j] >= thr) ? 1u : 0u;
+    }
+    const uint32_t incl = block_incl_scan(c, wsum);
+    if (t == kThreads - 1) *total_s = incl;
+    uint32_t o = (uint32_t)cur + incl - c;
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if (key[j] != 0 && key[j] >= thr) buf[o++] = key[j];
+    __syncthreads();
+    cur += *total_s;
+  }
+  uint64_t lo, hi;
+  block_key_range(buf, cur, &lo, &hi);
+  select_and_write<M>(buf, cur, q, a, range_top_bit(lo, hi), hi, sel, hist, bprefix, bneed, nsel);
 }
 
 template <int M>
@@ -1770,11 +1887,14 @@ __device__ __forceinline__ uint64_t cand_key(uint64_t e, int32_t xq, float Tq, c
   return make_key<M>(score_f32<M>(Tq, lut[xc], lut[xq + xc - xab]), idx);
 }
 
-// Slot entries of the query-lane scans are raw (x_c, x_ab, row) and are
-// scored here (RAW); the row-lane scan and the sample pass store final keys.
-template <int M, bool RAW, bool LUT>
+// Select of query q. Slot entries of the query-lane scans are raw
+// (x_c, x_ab, row) and are scored here (RAW); the row-lane scan and the
+// sample pass store final keys. PER: slabs per thread (n_slabs <= 256 * PER).
+template <int M, bool RAW, bool LUT, int PER>
 __device__ __forceinline__ void select_query(const TopkArgs& a, int64_t q) {
-  extern __shared__ uint64_t sm[];  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats
+  // sel[kpad], keys[lds_keys], then (LUT) T[0..N] as floats; or, for the
+  // whole-corpus fallback, the layout of fallback_query
+  extern __shared__ uint64_t sm[];
   __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t wsum[kThreads / kWave];
   __shared__ uint64_t bprefix;
@@ -1782,84 +1902,103 @@ __device__ __forceinline__ void select_query(const TopkArgs& a, int64_t q) {
   __shared__ uint32_t nsel;
   __shared__ uint32_t total_s;
   __shared__ uint32_t above_s;
-  constexpr int PER = kMaxSlabs / kThreads;  // slabs per thread
-  constexpr int CB = 4;                       // slot planes loaded as one batch
+  __shared__ uint32_t smin_s, smax_s;
+  constexpr int RE = 6;  // scan entries per thread read in one round (more: one by one after)
   const int t = threadIdx.x;
   uint64_t* region = a.cands + (size_t)q * a.kmax;  // S sample slots, then the slot planes
   const uint64_t* slots = region + a.S;
-  // 1. one round of loads: the overflow flag, the slab counts, slot plane 0
-  // (most survivors; read whole, it is one dense run), the T table. Thread t
-  // owns slabs t, t + 256, ..., so every count and plane load is one
-  // coalesced run per wave.
+  // 1. first round of loads: the query's constants, the overflow flag, the
+  // slab counts, the first 256 sample candidates, T into LDS. Thread t owns
+  // slabs t, t + 256, ..., so the count loads are one coalesced run per wave.
+  const float Tq = a.qc[q].Tq;
+  const int32_t xq = a.qc[q].xq;
+  const uint32_t tau_key = a.qc[q].tau_key;
   const int32_t qovf = a.qovf[q];
   const int64_t ns = a.cnts[q];
-  const int32_t xq = a.popQ[q];
   const int32_t* sc = a.scnt + (size_t)q * a.n_slabs;
+  const uint64_t s0 = t < a.S ? region[t] : 0;
   uint32_t cnt[PER], part = 0;
-  uint64_t v0[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int64_t i = (int64_t)u * kThreads + t;
     cnt[u] = i < a.n_slabs ? (uint32_t)sc[i] : 0u;
-    v0[u] = i < a.n_slabs ? slots[i] : 0;
   }
   float* lut_s = reinterpret_cast<float*>(sm + a.kpad + a.lds_keys);
-  if (LUT)  // read after the barriers of the count below
-    for (int x = t; x <= a.N; x += kThreads) lut_s[x] = a.t32[x];
+  if (LUT) copy_words_to_lds(reinterpret_cast<uint32_t*>(lut_s), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
   const float* lut = LUT ? lut_s : a.t32;
-  if (t == 0) above_s = 0;
+  if (t == 0) {
+    above_s = 0;
+    smin_s = ~0u;
+    smax_s = 0;
+  }
 #pragma unroll
   for (int u = 0; u < PER; ++u) part += cnt[u];
-  const uint32_t incl = block_incl_scan(part, wsum);
+  const uint32_t incl = block_incl_scan(part, wsum);  // (its barriers also publish T)
   if (t == kThreads - 1) total_s = incl;
   __syncthreads();
-  if (qovf) {  // block-uniform: a slab overflowed its slots, the fallback kernel ranks the query
-    if (t == 0) {
-      a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
-      __threadfence();  // the entry before this block's ticket (select_body)
-    }
+  if (qovf) {  // block-uniform: a slab overflowed its slots
+    fallback_query<M>(a, q, sm, hist, &bprefix, &bneed, &nsel, wsum, &total_s);
     return;
   }
   const int64_t n = ns + total_s;
   uint64_t* sel = sm;
-  const float Tq = a.t32[xq];
-  // keys at or above tau (the check below), counted as they are written
-  const uint64_t thr = a.kt < a.k ? (uint64_t)a.qc[q].tau_key << 32 : 0;
-  uint32_t above = 0;
+  // keys at or above tau (the check below) and the range of score keys,
+  // noted as the keys are written
+  const uint64_t thr = a.kt < a.k ? (uint64_t)tau_key << 32 : 0;
+  uint32_t above = 0, smin = ~0u, smax = 0;
+  auto note = [&](uint64_t key) {
+    above += key >= thr ? 1u : 0u;
+    const uint32_t sk = (uint32_t)(key >> 32);
+    smin = sk < smin ? sk : smin;
+    smax = sk > smax ? sk : smax;
+  };
   auto key_of = [&](uint64_t e) { return RAW ? cand_key<M>(e, xq, Tq, lut, a) : e; };
-  auto slot = [&](uint32_t c, int u) { return slots[(size_t)c * a.n_slabs + (size_t)u * kThreads + t]; };
   uint64_t* keys;
   if (n <= a.lds_keys) {
-    // 2a. into LDS: each thread writes its slabs' entries at its offset in
-    // the count's scan; planes 0..CB-1 are loaded as one batch, deeper slots
-    // (rare) after
+    // 2a. into LDS, in two steps so that every thread handles about the same
+    // number of entries (slab counts vary). First each thread writes, at the
+    // position of every entry of its slabs (from the count's scan), where the
+    // entry lives: (slot, slab). Then, after a barrier, thread t reads
+    // positions ns + t, ns + t + 256, ...: their entries arrive in one round
+    // of loads, are scored, and replace their own map words.
     keys = sm + a.kpad;
-    for (int64_t i = t; i < ns; i += kThreads) {
-      const uint64_t key = region[i];
-      keys[i] = key;
-      above += key >= thr ? 1u : 0u;
-    }
-    uint64_t v[CB][PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) v[0][u] = v0[u];
-#pragma unroll
-    for (int c = 1; c < CB; ++c)
-#pragma unroll
-      for (int u = 0; u < PER; ++u) v[c][u] = cnt[u] > (uint32_t)c ? slot(c, u) : 0;
-    uint32_t o = (uint32_t)ns + incl - part;
-    auto put = [&](uint32_t at, uint64_t e) {
-      const uint64_t key = key_of(e);
-      keys[at] = key;
-      above += key >= thr ? 1u : 0u;
-    };
+    uint32_t o = (uint32_t)ns + incl - part;  // the thread's first position in the count's scan
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-#pragma unroll
-      for (int c = 0; c < CB; ++c)
-        if (cnt[u] > (uint32_t)c) put(o + c, v[c][u]);
-#pragma unroll 4
-      for (uint32_t c = CB; c < cnt[u]; ++c) put(o + c, slot(c, u));
+      const uint32_t slab = (uint32_t)(u * kThreads + t);
+      for (uint32_t c = 0; c < cnt[u]; ++c) keys[o + c] = ((uint64_t)c << 32) | slab;
       o += cnt[u];
+    }
+    for (int64_t i = t; i < ns; i += kThreads) {
+      const uint64_t key = i < kThreads ? s0 : region[i];
+      keys[i] = key;
+      note(key);
+    }
+    __syncthreads();
+    const uint32_t nsc = total_s;  // scan entries
+    auto fetch = [&](uint32_t e) {
+      const uint64_t m = keys[ns + e];
+      return slots[(size_t)(m >> 32) * a.n_slabs + (uint32_t)m];
+    };
+    uint64_t v[RE];
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const uint32_t e = (uint32_t)(r * kThreads + t);
+      v[r] = e < nsc ? fetch(e) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RE; ++r) {
+      const uint32_t e = (uint32_t)(r * kThreads + t);
+      if (e < nsc) {
+        const uint64_t key = key_of(v[r]);
+        keys[ns + e] = key;
+        note(key);
+      }
+    }
+    for (uint32_t e = RE * kThreads + t; e < nsc; e += kThreads) {
+      const uint64_t key = key_of(fetch(e));
+      keys[ns + e] = key;
+      note(key);
     }
   } else {
     // 2b. in place, one slot plane at a time (keys in plane order). Plane
@@ -1867,6 +2006,7 @@ __device__ __forceinline__ void select_query(const TopkArgs& a, int64_t q) {
     // below c: E <= c * n_slabs and n_c <= n_slabs, so they stay below plane
     // c + 1's sources, and every read of plane c comes before a write of it.
     keys = region;
+    auto slot = [&](uint32_t c, int u) { return slots[(size_t)c * a.n_slabs + (size_t)u * kThreads + t]; };
     uint32_t cm = 0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) cm = cnt[u] > cm ? cnt[u] : cm;
@@ -1878,84 +2018,45 @@ __device__ __forceinline__ void select_query(const TopkArgs& a, int64_t q) {
       for (int u = 0; u < PER; ++u) m += cnt[u] > c ? 1u : 0u;
       const uint32_t pincl = block_incl_scan(m, wsum);
       if (t == kThreads - 1) total_s = pincl;
-      uint64_t v[PER];
+      uint64_t w[PER];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) v[u] = cnt[u] > c ? slot(c, u) : 0;
+      for (int u = 0; u < PER; ++u) w[u] = cnt[u] > c ? slot(c, u) : 0;
       __syncthreads();
       uint32_t o = E + pincl - m;
 #pragma unroll
       for (int u = 0; u < PER; ++u)
         if (cnt[u] > c) {
-          const uint64_t key = key_of(v[u]);
+          const uint64_t key = key_of(w[u]);
           keys[o++] = key;
-          above += key >= thr ? 1u : 0u;
+          note(key);
         }
       E += total_s;
     }
-    for (int64_t i = t; i < ns; i += kThreads) above += region[i] >= thr ? 1u : 0u;  // the sample keys stay in place
+    for (int64_t i = t; i < ns; i += kThreads) note(region[i]);  // the sample keys stay in place
   }
-  if (above) atomicAdd(&above_s, above);
+  smin = wave_min_u32(smin);
+  smax = wave_max_u32(smax);
+  above = wave_sum_u32(above);
+  if (t % kWave == 0) {
+    atomicMin(&smin_s, smin);
+    atomicMax(&smax_s, smax);
+    atomicAdd(&above_s, above);
+  }
   __syncthreads();
   // tau check: with at least k candidates scoring >= tau the true k-th best
   // score is >= tau, and every row scoring >= tau is a candidate (with
   // kt = k, tau is a lower bound by construction and thr = 0 counts all)
-  if (above_s < (uint32_t)a.k) {  // block-uniform: the whole-corpus fallback ranks the query
-    if (t == 0) {
-      a.ovf[2 + atomicAdd(a.ovf, 1)] = (int32_t)q;
-      __threadfence();  // the entry before this block's ticket (select_body)
-    }
+  if (above_s < (uint32_t)a.k) {  // block-uniform
+    fallback_query<M>(a, q, sm, hist, &bprefix, &bneed, &nsel, wsum, &total_s);
     return;
   }
-  select_and_write<M>(keys, n, q, a, sel, hist, &bprefix, &bneed, &nsel);
-}
-
-// ---- fallback: whole-corpus selection for overflowed queries ----------------
-template <int M>
-__device__ __forceinline__ void fallback_body(const TopkArgs& a, int64_t b, int64_t nb) {
-  extern __shared__ uint64_t sm[];  // sel[kpad], then qw[W64]
-  __shared__ uint32_t hist[2 * kThreads];
-  __shared__ uint64_t bprefix;
-  __shared__ int64_t bneed;
-  __shared__ uint32_t nsel;
-  const int W64 = a.W32 / 2;
-  uint64_t* sel = sm;
-  uint64_t* qw = sm + a.kpad;
-  uint64_t* keys = a.scratch + (size_t)b * a.nC;
-  const int32_t n_ovf = a.ovf[0];
-  for (int64_t i = b; i < n_ovf; i += nb) {
-    const int64_t q = a.ovf[2 + i];
-    const uint64_t* qrow = a.Q + (size_t)q * W64;
-    for (int w = threadIdx.x; w < W64; w += kThreads) qw[w] = qrow[w];
-    const int32_t xq = a.popQ[q];
-    const float Tq = a.t32[xq];
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < a.nC; i += kThreads) {
-      const int32_t xab = and_popcount_row(qw, a.C + (size_t)i * W64, W64);
-      const int32_t xc = a.popC[i];
-      const float sc = score_f32<M>(Tq, a.t32[xc], a.t32[xq + xc - xab]);
-      keys[i] = make_key<M>(sc, (uint32_t)i);
-    }
-    __syncthreads();
-    select_and_write<M>(keys, a.nC, q, a, sel, hist, &bprefix, &bneed, &nsel);
-  }
-}
-
-// Select of query q, then, in the block that finishes last (a ticket taken
-// after each block's overflow entries are in place), the whole-corpus
-// fallback for every query that overflowed or failed the tau check: with no
-// such query that costs one atomic per block and no extra launch.
-template <int M, bool RAW, bool LUT>
-__device__ __forceinline__ void select_body(const TopkArgs& a, int64_t q) {
-  __shared__ uint32_t last_s;
-  select_query<M, RAW, LUT>(a, q);
-  __syncthreads();
-  // a block that queued its query fenced the entry before this ticket; the
-  // others have nothing to publish
-  if (threadIdx.x == 0) last_s = atomicAdd(&a.ovf[1], 1) == (int32_t)(a.nQ - 1) ? 1u : 0u;
-  __syncthreads();
-  if (!last_s) return;  // block-uniform
-  __threadfence();      // every other block's entries are visible
-  if (__builtin_amdgcn_readfirstlane(*(volatile int32_t*)a.ovf) > 0) fallback_body<M>(a, 0, 1);
+  KeyCompress xf;
+  xf.base = smin_s;
+  xf.b = a.nC > 1 ? 32 - __clz((int)(uint32_t)(a.nC - 1)) : 0;
+  xf.mask = (uint32_t)((1ull << xf.b) - 1);
+  const uint32_t span = smax_s - smin_s;
+  const int hb = xf.b + (span ? 32 - __clz((int)span) : 0);
+  select_and_write<M>(keys, n, q, a, hb, 0, sel, hist, &bprefix, &bneed, &nsel, xf);
 }
 
 // ---- grouped launches ---------------------------------------------------------
@@ -2046,19 +2147,15 @@ template <bool ONE, int M, int W32T>
 __global__ __launch_bounds__(kThreads) void topk_scan_rows_kernel(GroupArgs g) {
   BS_GROUP_LOOP((scan_rows_body<M, W32T>(a, lb)))
 }
-template <bool ONE, int M, bool RAW, bool LUT>
+template <bool ONE, int M, bool RAW, bool LUT, int PER>
 __global__ __launch_bounds__(kThreads) void topk_select_kernel(GroupArgs g) {
-  BS_GROUP_LOOP((select_body<M, RAW, LUT>(a, lb)))
-}
-template <bool ONE, int M>
-__global__ __launch_bounds__(kThreads) void topk_fallback_kernel(GroupArgs g) {
-  BS_GROUP_LOOP((fallback_body<M>(a, lb, a.F)))
+  BS_GROUP_LOOP((select_query<M, RAW, LUT, PER>(a, lb)))
 }
 #undef BS_GROUP_LOOP
 
-enum Stage { kStSample = 0, kStSampleSelect, kStBound, kStScan, kStSelect, kStFallback, kStages };
-const char* const kStageTimer[kStages] = {"topk_sample", "topk_sample", "topk_bound",
-                                          "topk_scan",   "topk_select", "topk_fallback"};
+enum Stage { kStSample = 0, kStSampleSelect, kStBound, kStScan, kStSelect, kStages };
+const char* const kStageTimer[kStages] = {"topk_sample", "topk_sample_select", "topk_bound", "topk_scan",
+                                          "topk_select"};
 
 // The select kernel keeps T in LDS when it scores raw survivors and T is small.
 bool select_lut(const TopkArgs& a) { return a.sel_lut != 0; }
@@ -2077,24 +2174,24 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
       if (a.split) return (a.n_slabs / kSplitWaves) * a.nqb4;
       return a.n_slabs * a.nqb4;
     case kStSelect: return a.nQ;
-    default: return 0;  // the fallback runs in the select's last block
+    default: return 0;
   }
 }
 
 // Dynamic LDS bytes of one item in one stage.
 size_t stage_lds(const TopkArgs& a, int st) {
-  const bool lds_lut = a.N <= 16384;
+  const bool lds_lut = a.N < 16384;  // T (rounded up to 64 words) within 64 KB
   switch (st) {
-    case kStSample: return (lds_lut || (a.split && !a.mma)) ? (size_t)(a.N + 1) * 4 : 0;
-    case kStSampleSelect: return (size_t)a.S * 4;
-    case kStBound: return lds_lut ? (size_t)(a.N + 1) * 4 : 0;
-    case kStScan: return a.rows ? (size_t)(a.N + 1) * 4 : 0;
-    case kStSelect: {  // also room for the fallback (selected keys, then the query's words)
-      const size_t sel = (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8 + (select_lut(a) ? (size_t)(a.N + 1) * 4 : 0);
-      const size_t fb = (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
+    case kStSample: return (lds_lut || (a.split && !a.mma)) ? (size_t)round_up64(a.N + 1) * 4 : 0;
+    case kStSampleSelect: return (size_t)round_up64(a.S) * 4;
+    case kStBound: return lds_lut ? (size_t)round_up64(a.N + 1) * 4 : 0;
+    case kStScan: return a.rows ? (size_t)round_up64(a.N + 1) * 4 : 0;
+    case kStSelect: {  // also room for the whole-corpus fallback (selected keys, key buffer, query words)
+      const size_t sel = (size_t)a.kpad * 8 + (size_t)a.lds_keys * 8 + (select_lut(a) ? (size_t)round_up64(a.N + 1) * 4 : 0);
+      const size_t fb = ((size_t)2 * a.kpad + (size_t)kFbRowsPerThread * kThreads + (size_t)(a.W32 / 2)) * 8;
       return sel > fb ? sel : fb;
     }
-    default: return (size_t)a.kpad * 8 + (size_t)(a.W32 / 2) * 8;
+    default: return 0;
   }
 }
 
@@ -2102,7 +2199,7 @@ size_t stage_lds(const TopkArgs& a, int st) {
 template <bool ONE, int M>
 const void* stage_kernel(const TopkArgs& a, int st) {
   const int W32 = a.W32;
-  const bool lds_lut = a.N <= 16384;
+  const bool lds_lut = a.N < 16384;  // T (rounded up to 64 words) within 64 KB
   const bool pow2 = (W32 & (W32 - 1)) == 0;
   switch (st) {
     case kStSample:
@@ -2181,11 +2278,18 @@ const void* stage_kernel(const TopkArgs& a, int st) {
           default: return (const void*)topk_scan_generic_kernel<ONE, 64>;
         }
       }
-    case kStSelect:
-      if (a.rows) return (const void*)topk_select_kernel<ONE, M, false, false>;
-      return select_lut(a) ? (const void*)topk_select_kernel<ONE, M, true, true>
-                           : (const void*)topk_select_kernel<ONE, M, true, false>;
-    default: return (const void*)topk_fallback_kernel<ONE, M>;
+    case kStSelect: {
+      const bool wide = a.sel_per > 4;
+      if (a.rows)
+        return wide ? (const void*)topk_select_kernel<ONE, M, false, false, 8>
+                    : (const void*)topk_select_kernel<ONE, M, false, false, 4>;
+      if (select_lut(a))
+        return wide ? (const void*)topk_select_kernel<ONE, M, true, true, 8>
+                    : (const void*)topk_select_kernel<ONE, M, true, true, 4>;
+      return wide ? (const void*)topk_select_kernel<ONE, M, true, false, 8>
+                  : (const void*)topk_select_kernel<ONE, M, true, false, 4>;
+    }
+    default: return nullptr;
   }
 }
 
@@ -2228,14 +2332,12 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.t32w = nullptr;
   a.popQ = it.popQ;
   a.popC = it.popC;
-  a.ovf = reinterpret_cast<int32_t*>(ws + p.off_ovf);
   a.skeys = reinterpret_cast<uint32_t*>(ws + p.off_skeys);
   a.qc = reinterpret_cast<QConst*>(ws + p.off_qc);
   a.cnts = reinterpret_cast<int32_t*>(ws + p.off_cnts);
   a.cands = reinterpret_cast<uint64_t*>(ws + p.off_cands);
   a.scnt = reinterpret_cast<int32_t*>(ws + p.off_scnt);
   a.qovf = reinterpret_cast<int32_t*>(ws + p.off_qovf);
-  a.scratch = reinterpret_cast<uint64_t*>(ws + p.off_scratch);
   a.mtab = reinterpret_cast<uint16_t*>(ws + p.off_mtab);
   a.out_idx = it.out_idx;
   a.out_score = it.out_score;
@@ -2253,7 +2355,6 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.s_rblocks = p.s_rblocks;
   a.s_nqb = p.s_nqb;
   a.s_qb = p.s_qb;
-  a.F = p.F;
   a.N = it.N;
   a.W32 = it.N / 32;
   a.k = it.k;
@@ -2266,6 +2367,7 @@ void fill_args(TopkArgs& a, const Plan& p, const TopkItem& it, char* ws) {
   a.split = p.split ? 1 : 0;
   a.mma = p.mma ? 1 : 0;
   a.sel_lut = p.sel_lut ? 1 : 0;
+  a.sel_per = p.n_slabs <= 4 * kThreads ? 4 : 8;
 }
 
 }  // namespace
@@ -2335,14 +2437,15 @@ bs_status topk_group_create(const TopkItem* items, const TopkTune* tunes, int32_
     const Plan p = make_plan(items[i].nQ, items[i].nC, items[i].N, items[i].k, tunes ? tunes[i] : dflt);
     fill_args(G->args[i], p, items[i], static_cast<char*>(item_ws[i]));
   }
-  // classes: items that share every kernel variant (width, scan mode, queries per lane, select LUT)
+  // classes: items that share every kernel variant (width, scan mode, queries per lane, select LUT
+  // and slabs per thread)
   for (int32_t i = 0; i < n; ++i) {
     if (G->args[i].nQ == 0) continue;
     int32_t c = -1;
     for (size_t j = 0; j < G->classes.size(); ++j) {
       const TopkArgs& r = G->args[G->classes[j][0]];
       if (r.N == G->args[i].N && r.rows == G->args[i].rows && r.mma == G->args[i].mma && r.qpl == G->args[i].qpl &&
-          r.sel_lut == G->args[i].sel_lut)
+          r.sel_lut == G->args[i].sel_lut && r.sel_per == G->args[i].sel_per)
         c = (int32_t)j;
     }
     if (c < 0) {
@@ -2504,9 +2607,9 @@ extern "C" bs_status bs_topk(const uint64_t* Q, const int32_t* popQ, int64_t nQ,
   fill_args(a, p, it, ws);
   if (N <= 1024 && !p.split) a.t32w = reinterpret_cast<float*>(ws + p.off_t32);
   hipStream_t s = as_stream(stream);
-  {
+  // up to N = 1024 the sample pass evaluates T itself (one launch fewer)
+  if (a.t32w == nullptr || !popQ || !popC) {
     ScopedTiming timing("topk_prep", s);
-    // up to N = 1024 the sample pass evaluates T itself (one launch fewer)
     if (a.t32w == nullptr) launch_lut(N, nullptr, reinterpret_cast<float*>(ws + p.off_t32), s);
     if (!popQ) launch_row_popcount(Q, nQ, N, reinterpret_cast<int32_t*>(ws + p.off_popq), s);
     if (!popC) launch_row_popcount(C, nC, N, reinterpret_cast<int32_t*>(ws + p.off_popc), s);
