@@ -348,13 +348,15 @@ __device__ __forceinline__ uint32_t block_max_u32(uint32_t v, uint32_t* wsum) {
 // shares its round trip with the loads issued before it (the caller's barrier
 // publishes the words). Lanes past n re-read word n - 1 into the padding:
 // dst has room for n rounded up to 64 words.
-__device__ __forceinline__ void copy_words_to_lds(uint32_t* dst, const uint32_t* src, int64_t n) {
+// With wait = false the copy is left in flight (a later copy's wait, or the
+// caller's, completes it).
+__device__ __forceinline__ void copy_words_to_lds(uint32_t* dst, const uint32_t* src, int64_t n, bool wait = true) {
   const int lane = threadIdx.x % kWave;
   for (int64_t j = threadIdx.x / kWave; j * kWave < n; j += kThreads / kWave) {
     const int64_t i = j * kWave + lane;
     __builtin_amdgcn_global_load_lds(src + (i < n ? i : n - 1), dst + j * kWave, 4, 0, 0);
   }
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+  if (wait) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
 }
 
 struct KeyIdentity {
@@ -765,7 +767,7 @@ __device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx,
 // of the scan filter.
 template <int M>
 __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
-  extern __shared__ uint32_t keys[];  // [S]
+  extern __shared__ uint32_t keys[];  // [S rounded up to 64]
   __shared__ uint32_t hist[2 * kThreads];
   __shared__ uint32_t bprefix;
   __shared__ int64_t bneed;
@@ -826,6 +828,51 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
 // m is clamped to [0, 65535]: lowering it only admits more candidates.
 constexpr int kBoundX = 16;  // table rows (x_c values) per block of the threshold kernel
 
+// m[x_c][q] of one query for the table rows xc[r] (r < R, xc[r] <= N + 1):
+// X = max{x in [0, N] : T(x) <= bound} (T non-decreasing), or -1, for the R
+// rows at once by a search whose steps depend only on N (so every row and
+// lane takes the same steps and every read is inside the table), each step
+// issuing one table read per row before using any. Row N + 1, and every row
+// of a query past the batch (q_ok false), is 65535: no count of N < 65536
+// reaches it.
+template <int M, int R>
+__device__ __forceinline__ void bound_rows(const float* lut, int32_t N, const QConst& k, bool q_ok, const int (&xc)[R],
+                                           uint16_t (&m)[R]) {
+  float bnd[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const float Tc = lut[xc[r] < N ? xc[r] : N];
+    float bound = fmaf(k.Tq + Tc, k.A, k.C);
+    if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
+    bnd[r] = bound;
+  }
+  int base[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) base[r] = 0;
+  for (int len = N + 1; len > 1;) {  // the count of x <= X lies in [base, base + len]
+    const int half = len >> 1;
+    float tv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) tv[r] = lut[base[r] + half];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) base[r] = tv[r] <= bnd[r] ? base[r] + half : base[r];
+    len -= half;
+  }
+  float tv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) tv[r] = lut[base[r]];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    m[r] = 65535;
+    if (q_ok && xc[r] <= N) {
+      const int X = base[r] + (tv[r] <= bnd[r] ? 1 : 0) - 1;
+      const int64_t mm = (int64_t)k.xq + xc[r] - X;
+      m[r] = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
+    }
+  }
+}
+
 template <int M, bool LDS_LUT>
 __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut_s[];
@@ -843,46 +890,18 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
   constexpr int RW = kThreads / kWave;
   constexpr int RPT = kBoundX / RW;  // table rows per thread
   const int wid = threadIdx.x / kWave;
-  float bnd[RPT];
+  int xc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int xc = (int)by * kBoundX + wid + r * RW;
-    const float Tc = lut[xc < a.N ? xc : a.N];
-    float bound = fmaf(k.Tq + Tc, k.A, k.C);
-    if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
-    bnd[r] = bound;
+    const int x = (int)by * kBoundX + wid + r * RW;
+    xc[r] = x <= a.N + 1 ? x : a.N + 1;
   }
-  // X = max{x in [0, N] : T(x) <= bound} (T non-decreasing), or -1, for the
-  // thread's rows at once: a search whose steps depend only on N (so every
-  // row and lane takes the same steps and every read is inside the table),
-  // each step issuing one table read per row before using any
-  int base[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) base[r] = 0;
-  for (int len = a.N + 1; len > 1;) {  // the count of x <= X lies in [base, base + len]
-    const int half = len >> 1;
-    float tv[RPT];
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) tv[r] = lut[base[r] + half];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) base[r] = tv[r] <= bnd[r] ? base[r] + half : base[r];
-    len -= half;
-  }
-  float tv[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) tv[r] = lut[base[r]];
+  uint16_t m[RPT];
+  bound_rows<M, RPT>(lut, a.N, k, q_ok, xc, m);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int xc = (int)by * kBoundX + wid + r * RW;
-    if (xc > a.N + 1) break;
-    uint16_t m = 65535;  // row N + 1 and queries past the batch: no count of N < 65536 reaches it
-    if (q_ok && xc <= a.N) {
-      const int X = base[r] + (tv[r] <= bnd[r] ? 1 : 0) - 1;
-      const int64_t mm = (int64_t)k.xq + xc - X;
-      m = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
-    }
-    a.mtab[(size_t)xc * a.nQp + qi] = m;
+    const int x = (int)by * kBoundX + wid + r * RW;
+    if (x <= a.N + 1) a.mtab[(size_t)x * a.nQp + qi] = m[r];
   }
 }
 
@@ -1574,13 +1593,61 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
 template <int M, int KCT, bool LDS_LUT>
 __device__ __forceinline__ void sample_mma_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut_s[];
+  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int c = lane % 32, h = lane / 32;
+  const int64_t q0 = by * kWave + 32 * (wid / 2);  // the wave's 32 queries
+  const int64_t i0 = bx * kWave + 32 * (wid % 2);  // the wave's 32 sampled rows
+  const bool live = q0 < a.nQ && i0 < a.S;          // wave-uniform
+  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 8;
+  const uint32_t rowb = (uint32_t)W32 * 4u;
+  // operand row c holds query q0 + 16 ((c / 4) % 2) + 4 (c / 8) + c % 4, so
+  // accumulator element e of lane (h, c) is query q0 + 16 h + e (as in the
+  // scan). Indices are clamped, so a wave past the batch loads in bounds.
+  int64_t qr = q0 + 16 * ((c / 4) % 2) + 4 * (c / 8) + c % 4;
+  qr = qr < a.nQ ? qr : a.nQ - 1;
+  const int64_t irow = i0 + c;
+  const int64_t crow = (irow < a.S ? irow : a.S - 1) * a.stride;
+  const char* qp = reinterpret_cast<const char*>(a.Q) + (size_t)qr * rowb + 16u * h;
+  const char* cp = reinterpret_cast<const char*>(a.C) + (size_t)crow * rowb + 16u * h;
+  // every load first (the first G chunks of both operands and the row
+  // weights), then T, so that building T overlaps the loads' round trip
+  constexpr int G = 4;  // chunks loaded as one batch
+  uint4 av[G], bv[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j)
+    if (j < KC) {
+      av[j] = *reinterpret_cast<const uint4*>(qp + 32u * j);
+      bv[j] = *reinterpret_cast<const uint4*>(cp + 32u * j);
+    }
+  const int32_t xc = a.popC[crow];
+  // the weights of the 16 queries of the lane's accumulator elements (query
+  // q0 + 16 h + e), loaded directly: two distinct addresses per load
+  int32_t xqe[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int64_t q = q0 + 16 * h + e;
+    xqe[e] = a.popQ[q < a.nQ ? q : a.nQ - 1];
+  }
   const float* lut = a.t32;
   if (LDS_LUT) {
     if (a.t32w) {  // small N: every block evaluates T, the first also stores it for the later passes
-      for (int x = threadIdx.x; x <= a.N; x += kThreads) {
-        const float v = (float)t_value(x, a.N);
-        lut_s[x] = v;
-        if (bx == 0 && by == 0) a.t32w[x] = v;
+      // TV entries per thread evaluated side by side (independent FP64 chains)
+      constexpr int TV = 5;
+      for (int x0 = threadIdx.x; x0 <= a.N; x0 += TV * kThreads) {
+        float v[TV];
+#pragma unroll
+        for (int j = 0; j < TV; ++j) {
+          const int x = x0 + j * kThreads;
+          v[j] = x <= a.N ? (float)t_value(x, a.N) : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < TV; ++j) {
+          const int x = x0 + j * kThreads;
+          if (x <= a.N) {
+            lut_s[x] = v[j];
+            if (bx == 0 && by == 0) a.t32w[x] = v[j];
+          }
+        }
       }
     } else {
       copy_words_to_lds(reinterpret_cast<uint32_t*>(lut_s), reinterpret_cast<const uint32_t*>(a.t32), a.N + 1);
@@ -1588,49 +1655,33 @@ __device__ __forceinline__ void sample_mma_body(const TopkArgs& a, int64_t bx, i
     __syncthreads();
     lut = lut_s;
   }
-  const int lane = threadIdx.x % kWave, wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int c = lane % 32, h = lane / 32;
-  const int64_t q0 = by * kWave + 32 * (wid / 2);  // the wave's 32 queries
-  const int64_t i0 = bx * kWave + 32 * (wid % 2);  // the wave's 32 sampled rows
-  if (q0 >= a.nQ || i0 >= a.S) return;  // wave-uniform; no barrier follows
-  const int W32 = a.W32, KC = KCT > 0 ? KCT : W32 / 8;
-  const uint32_t rowb = (uint32_t)W32 * 4u;
-  // operand row c holds query q0 + 16 ((c / 4) % 2) + 4 (c / 8) + c % 4, so
-  // accumulator element e of lane (h, c) is query q0 + 16 h + e (as in the scan)
-  int64_t qr = q0 + 16 * ((c / 4) % 2) + 4 * (c / 8) + c % 4;
-  qr = qr < a.nQ ? qr : a.nQ - 1;
-  const int64_t irow = i0 + c;
-  const int64_t crow = (irow < a.S ? irow : a.S - 1) * a.stride;
-  const char* qp = reinterpret_cast<const char*>(a.Q) + (size_t)qr * rowb + 16u * h;
-  const char* cp = reinterpret_cast<const char*>(a.C) + (size_t)crow * rowb + 16u * h;
+  if (!live) return;  // no barrier follows
   bs_v16f acc;
 #pragma unroll
   for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
-  uint4 av = *reinterpret_cast<const uint4*>(qp), bv = *reinterpret_cast<const uint4*>(cp);
-  constexpr int KU = KCT > 0 && KCT <= 4 ? KCT : 1;
-#pragma unroll KU
-  for (int ch = 0; ch < KC; ++ch) {
-    uint4 an = av, bn = bv;
-    if (ch + 1 < KC) {  // the next chunk loads while this one is multiplied
-      an = *reinterpret_cast<const uint4*>(qp + 32u * (ch + 1));
-      bn = *reinterpret_cast<const uint4*>(cp + 32u * (ch + 1));
+  for (int c0 = 0; c0 < KC; c0 += G) {
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if (c0 + j < KC) {
+        const uint32_t aw[4] = {av[j].x, av[j].y, av[j].z, av[j].w}, bw[4] = {bv[j].x, bv[j].y, bv[j].z, bv[j].w};
+        acc = mma_class<0>(fp4_class<0>(aw), fp4_class<0>(bw), acc);
+        acc = mma_class<1>(fp4_class<1>(aw), fp4_class<1>(bw), acc);
+        acc = mma_class<2>(fp4_class<2>(aw), fp4_class<2>(bw), acc);
+        acc = mma_class<3>(fp4_class<3>(aw), fp4_class<3>(bw), acc);
+      }
+    if (c0 + G < KC) {  // the next batch of chunks (wide sketches)
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if (c0 + G + j < KC) {
+          av[j] = *reinterpret_cast<const uint4*>(qp + 32u * (c0 + G + j));
+          bv[j] = *reinterpret_cast<const uint4*>(cp + 32u * (c0 + G + j));
+        }
     }
-    const uint32_t aw[4] = {av.x, av.y, av.z, av.w}, bw[4] = {bv.x, bv.y, bv.z, bv.w};
-    acc = mma_class<0>(fp4_class<0>(aw), fp4_class<0>(bw), acc);
-    acc = mma_class<1>(fp4_class<1>(aw), fp4_class<1>(bw), acc);
-    acc = mma_class<2>(fp4_class<2>(aw), fp4_class<2>(bw), acc);
-    acc = mma_class<3>(fp4_class<3>(aw), fp4_class<3>(bw), acc);
-    av = an;
-    bv = bn;
   }
-  const int32_t xc = a.popC[crow];
   const float Tc = lut[xc];
-  // lane l holds the weight of query q0 + l % 32; element e of half h reads lane 16 h + e
-  const int64_t ql = q0 + lane % 32 < a.nQ ? q0 + lane % 32 : a.nQ - 1;
-  const int32_t xql = a.popQ[ql];
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
-    const int32_t xq = __shfl(xql, 16 * h + e);
+    const int32_t xq = xqe[e];
     const float sc = score_f32<M>(lut[xq], Tc, lut[xq + xc - (int32_t)acc[e]]);
     const int64_t q = q0 + 16 * h + e;
     if (irow < a.S && q < a.nQ) a.skeys[(size_t)q * a.S + irow] = score_key<M>(sc);
