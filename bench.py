@@ -612,6 +612,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
     ap.add_argument("--no-dense", action="store_true", help="skip the small-corpus all-pairs estimate run")
     ap.add_argument("--graph", action="store_true", help="time replays of the step recorded into a HIP graph")
+    ap.add_argument("--vector-scan", action="store_true",
+                    help="count pairs on the vector ALU at every width (profiling the VALU scan; the default puts "
+                         "widths that are multiples of 256 on the matrix cores)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device-to-device copy of this many bytes (counter calibration)")
     ap.add_argument("--ingest-counters", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_BYTES"),
@@ -645,6 +648,9 @@ def main():
     widths = [args.N] + [n for n in others if n != args.N]
     corpus, queries, pis, dev_in = make_inputs(widths, dev)
     nC, nQ, k = corpus.n, queries.n, args.k
+    if args.vector_scan:
+        from paper_1910_04658_amd import binding as bs
+        bs.debug_set_topk_mma(False)
 
     results = {}
     for i, N in enumerate(widths):
@@ -664,7 +670,7 @@ def main():
         if "topk_scan" not in kt:
             return None
         t = kt["topk_scan"]["avg_ms"] / 1e3
-        if N % 256 == 0:
+        if N % 256 == 0 and not args.vector_scan:
             # matrix-core scan: x_ab of every scanned pair is an N-term 0/1
             # product, 2 N flops on FP4 operands
             fl = 2 * nQ * (nC - S) * N
@@ -715,8 +721,10 @@ def main():
                    "n_corpus": nC, "n_queries": nQ, "d": corpus.d, "k": k,
                    "row_length": "round(lognormal), mean 230, sd 150",
                    "feature_popularity": "Zipf(1.1)", "score_dtype": "f32",
-                   "pair_counts": "exact integers: 0/1 FP4 matrix-core operands with FP32 accumulators "
-                                  "(N a multiple of 256), else VALU AND + popcount", "parallelism": "single GPU"},
+                   "pair_counts": ("exact integers: VALU AND + popcount at every width (--vector-scan)"
+                                   if args.vector_scan else
+                                   "exact integers: 0/1 FP4 matrix-core operands with FP32 accumulators "
+                                   "(N a multiple of 256), else VALU AND + popcount"), "parallelism": "single GPU"},
         "sketched_vectors_per_s": sketch_rate(kt),
         "pair_estimates_per_s": value,
         "kernels_ms": {n: v["avg_ms"] for n, v in kt.items()},

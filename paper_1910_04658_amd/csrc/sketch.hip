@@ -340,6 +340,9 @@ __global__ void pack_map_kernel(const int32_t* __restrict__ pi, int64_t d, int32
   if (bad && err) atomicOr(err, (int32_t)BS_FLAG_MAP);
 }
 
+// RA: index chunks aligned to each wave's element run (short windows) rather
+// than to each window's start (see the index-stream comment below).
+template <bool RA>
 __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(SketchLdsArgs A) {
   extern __shared__ uint32_t lds[];
   const int bits = A.bits;
@@ -444,17 +447,27 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
     p_next = (lane <= g0) ? a.indptr[rw0 + lane] : 0;
   }
   // The wave's elements are one contiguous run (its rows are consecutive), so
-  // the index stream is software-pipelined across windows: while a chunk of
-  // 1,024 indices is processed, the next chunk's loads are in flight.
-  // Prefetch positions are clamped into [0, nnz), so a malformed indptr can
-  // only waste a prefetch, never read out of bounds; a chunk whose start
-  // differs from the prefetched one reloads.
+  // the index stream is software-pipelined in 1,024-element chunks: while one
+  // is processed, the next one's loads are in flight. With RA (windows
+  // shorter than two chunks on average: wide sketches leave room for few
+  // rows) the chunks are aligned to the run's start: a chunk that straddles
+  // windows is loaded once and serves each of them (the slices outside a
+  // window are skipped, the lanes outside it masked), so every index is
+  // fetched once. Otherwise the chunks start at each window's start, which
+  // re-fetches part of a chunk per window but processes no chunk twice (the
+  // kernel is then bound by LDS, not by the fetch). Prefetch positions are
+  // clamped into [0, nnz), so a malformed indptr can only waste a prefetch,
+  // never read out of bounds; a chunk whose start differs from the
+  // prefetched one reloads.
   const int64_t nnz = a.nnz;
   const int64_t wave_end = rw0 < rw1 ? (int64_t)a.indptr[rw1] : 0;  // prefetch bound only
   // Element positions fit 32 bits (nnz <= INT32_MAX), so every position and
   // row-start comparison below is a scalar 32-bit operation.
-  uint32_t nidx[kUnrollLds];
-  uint32_t pf_base = UINT32_MAX;  // start of the chunk whose indices are in flight
+  constexpr uint32_t CH = kWave * kUnrollLds;  // elements per chunk
+  uint32_t nidx[kUnrollLds], idx[kUnrollLds];
+  uint32_t pf_base = UINT32_MAX;   // start of the chunk whose indices are in flight (nidx)
+  uint32_t cur_base = UINT32_MAX;  // start of the chunk in idx
+  uint32_t run0 = 0;               // the wave's first element: run-aligned chunks start at run0 + k CH
   auto prefetch = [&](uint32_t b) {
     pf_base = b;
     if ((int64_t)b + (int64_t)kWave * kUnrollLds <= nnz) {
@@ -472,7 +485,8 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
   };
   if (rw0 < rw1 && nnz > 0) {
     const int32_t b = __builtin_amdgcn_readfirstlane(p_next);
-    prefetch(b < 0 ? 0u : (uint32_t)b);
+    run0 = b < 0 ? 0u : (uint32_t)b;
+    prefetch(run0);
   }
   const uint32_t row_bytes = (uint32_t)W32 * 4u;
   const uint32_t sk_b = lds_addr(sk), table_b = lds_addr(table);
@@ -506,25 +520,31 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
       // lanes 1 .. g-1 of p hold the window's row starts after the first
       const uint64_t starts = __ballot(lane >= 1 && lane < g);
       uint32_t c_prev = 0;  // row starts before the current slice
-      for (uint32_t base = e0; base < e1; base += kWave * kUnrollLds) {
-        // Element u of lane l sits at base + u*64 + l. A full chunk has no
-        // per-element branches; the last chunk of a window skips its empty
-        // 64-element slices with a uniform branch and masks the lanes past
-        // the end of the partial one. An index outside [0, d) is flagged and
-        // clamped (the output is then undefined) so the table read stays
-        // inside LDS.
-        if (pf_base != base) prefetch(base);
-        uint32_t idx[kUnrollLds];
+      // the run-aligned chunk holding e0 (a window starting before the run,
+      // possible only with a malformed indptr, takes its own chunk), or e0
+      const uint32_t base0 = RA && e0 >= run0 ? run0 + (e0 - run0) / CH * CH : e0;
+      for (uint32_t base = base0; base < e1; base += CH) {
+        // Element u of lane l sits at base + u*64 + l; the window holds
+        // positions [e0, e1). A chunk inside the window has no per-element
+        // branches; otherwise the 64-element slices outside the window are
+        // skipped with a uniform branch and the lanes of the partial slices
+        // masked. An index outside [0, d) is flagged and clamped (the output
+        // is then undefined) so the table read stays inside LDS.
+        if (!RA || cur_base != base) {
+          if (pf_base != base) prefetch(base);
 #pragma unroll
-        for (int u = 0; u < kUnrollLds; ++u) idx[u] = nidx[u];
-        {
-          const uint32_t next = e1 - base > (uint32_t)(kWave * kUnrollLds) ? base + kWave * kUnrollLds : e1;
+          for (int u = 0; u < kUnrollLds; ++u) idx[u] = nidx[u];
+          cur_base = base;
+          // the next chunk: the run's next, or (window-aligned) this window's
+          // next or else the next window's start
+          const uint32_t next = (RA || e1 - base > CH) ? base + CH : e1;
           if ((int64_t)next < wave_end) prefetch(next);
           else pf_base = UINT32_MAX;
         }
+        const uint32_t lo_off = RA && e0 > base ? e0 - base : 0u;  // first window position in the chunk
         auto chunk = [&](auto full_tag) {
           constexpr bool FULL = decltype(full_tag)::value;
-          const uint32_t rem = FULL ? (uint32_t)(kWave * kUnrollLds) : e1 - base;
+          const uint32_t rem = FULL ? CH : (e1 - base < CH ? e1 - base : CH);
           // Stage-row LDS byte address of each lane's element in slice u: the
           // row starts up to the slice's last element are counted with one
           // ballot; each start inside the slice moves the lanes at and past
@@ -551,6 +571,7 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             if (!FULL && (uint32_t)(h * H * kWave) >= rem) break;  // wave-uniform: the rest is past the end
+            if (!FULL && (uint32_t)((h + 1) * H * kWave) <= lo_off) continue;  // wave-uniform: before the window
             uint32_t bp[H], lo[H], hi[H];
 #pragma unroll
             for (int v = 0; v < H; ++v) {
@@ -560,6 +581,9 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
             }
 #pragma unroll
             for (int v = 0; v < H; ++v) {
+              const int u = h * H + v;
+              // wave-uniform: no table read for a slice outside the window
+              if (!FULL && ((uint32_t)((u + 1) * kWave) <= lo_off || (uint32_t)(u * kWave) >= rem)) continue;
               const lds_u32* tw = lds_ptr(table_b + ((bp[v] >> 5) << 2));
               lo[v] = tw[0];
               hi[v] = tw[1];
@@ -569,17 +593,20 @@ __global__ __launch_bounds__(kBigBlockWaves * kWave) void sketch_csr_lds_kernel(
             for (int v = 0; v < H; ++v) {
               const int u = h * H + v;
               if (!FULL && (uint32_t)(u * kWave) >= rem) break;  // wave-uniform
+              // wave-uniform: a slice before the window (it holds no row start)
+              if (!FULL && (uint32_t)((u + 1) * kWave) <= lo_off) continue;
               const uint32_t ro = slice_rows(u);
               // target in the low `bits` bits of t (higher bits are the next
               // entries): word t[bits-1:5] of the row, bit t[4:0]
               const uint32_t t = __builtin_amdgcn_alignbit(hi[v], lo[v], bp[v]);
               const uint32_t addr = ro + (__builtin_amdgcn_ubfe(t, 5, wbits) << 2);
-              if (FULL || (uint32_t)(u * kWave + lane) < rem)
+              const uint32_t pos = (uint32_t)(u * kWave + lane);
+              if (FULL || (pos < rem && pos >= lo_off))
                 __atomic_fetch_or(lds_ptr(addr), 1u << (t & 31), __ATOMIC_RELAXED);
             }
           }
         };
-        if (e1 - base >= (uint32_t)(kWave * kUnrollLds)) chunk(std::true_type());
+        if (lo_off == 0 && e1 - base >= CH) chunk(std::true_type());
         else chunk(std::false_type());
       }
     }
@@ -868,8 +895,15 @@ bs_status sketch_parts_impl(const bs_sketch_part* parts, int32_t n_parts, const 
     if (grid < 1) grid = 1;
     if ((size_t)lds <= (size_t)lds_max) {
       split_waves(parts, n_parts, grid * kBigBlockWaves, L.wave_off);
-      if (lds > 65536) (void)hipFuncSetAttribute((const void*)sketch_csr_lds_kernel,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      // short windows (on average under two index chunks): run-aligned chunks
+      int64_t rows = 0, nnz = 0;
+      for (int i = 0; i < n_parts; ++i) {
+        rows += parts[i].n_rows;
+        nnz += parts[i].nnz;
+      }
+      const bool ra = nnz * Gl < INT64_C(2) * kWave * kUnrollLds * rows;
+      const void* fn = ra ? (const void*)sketch_csr_lds_kernel<true> : (const void*)sketch_csr_lds_kernel<false>;
+      if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
       if (!packed) {
         const int64_t n_groups = (d + 31) / 32;
         ScopedTiming timing("sketch_pack", as_stream(stream));
@@ -877,8 +911,12 @@ bs_status sketch_parts_impl(const bs_sketch_part* parts, int32_t n_parts, const 
                            as_stream(stream), pi, d, N, bits, static_cast<uint32_t*>(workspace), err_flag);
       }
       ScopedTiming timing("sketch_csr", as_stream(stream));
-      hipLaunchKernelGGL(sketch_csr_lds_kernel, dim3((unsigned)grid), dim3(kBigBlockWaves * kWave), lds,
-                         as_stream(stream), L);
+      if (ra)
+        hipLaunchKernelGGL(sketch_csr_lds_kernel<true>, dim3((unsigned)grid), dim3(kBigBlockWaves * kWave), lds,
+                           as_stream(stream), L);
+      else
+        hipLaunchKernelGGL(sketch_csr_lds_kernel<false>, dim3((unsigned)grid), dim3(kBigBlockWaves * kWave), lds,
+                           as_stream(stream), L);
       return launch_status();
     }
   }
