@@ -217,13 +217,16 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
     p.s_nqb = (nQ + kWave - 1) / kWave;
     if (p.s_nqb < 1) p.s_nqb = 1;
   }
-  // LDS of the select kernel: room for 1.25x the expected candidate count
-  // (k * nC / S) plus 512, about four standard deviations of the count for
-  // k = 100 (a query with more candidates selects in place in its candidate
-  // region), and T when the kernel scores raw survivors, all within 60 KB
+  // LDS of the select kernel: room for 2.25x the expected candidate count
+  // (kt * nC / S) plus 512, and T when the kernel scores raw survivors, all
+  // within 60 KB. The count is not Poisson: queries whose scores tie heavily
+  // at tau have many more candidates (in a 1,000 x 100,000 batch the largest
+  // is 2.1x the mean), and a query that does not fit selects in place in its
+  // candidate region, several times slower; the kernel's time is its slowest
+  // block's
   {
     const double expect = p.S > 0 ? (double)p.kt * (double)nC / (double)p.S : 0.0;
-    int64_t lk = ((int64_t)(1.25 * expect) + 512 + 255) / 256 * 256;
+    int64_t lk = ((int64_t)(2.25 * expect) + 512 + 255) / 256 * 256;
     p.lds_keys = lk < 1024 ? 1024 : (lk > kSelectLdsKeys ? kSelectLdsKeys : lk);
     int64_t kpad = 1;
     while (kpad < k) kpad <<= 1;
