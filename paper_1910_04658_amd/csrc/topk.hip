@@ -378,12 +378,19 @@ struct KeyIdentity {
 // resolved: the result is then the lower edge of the bin holding the k-th
 // key, a lower bound on it. `keys` may be in LDS or global memory; `hist`
 // holds 2 x 256 counters used in turn (the wave that scans one clears the
-// other), so a pass costs two block barriers. Block-wide call.
+// other), so a pass costs two block barriers. With `unique` (no two keys
+// equal), once the bin holding the k-th key has at most 2 KB of keys they
+// are gathered into `hist` and the one with exactly need - 1 larger keys
+// among them is the k-th key: one gather and one count instead of the
+// remaining passes (prefix is then that key and *pmask_out all ones).
+// Block-wide call.
 template <typename K, typename Xf = KeyIdentity>
 __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* hist, K* bcast_prefix,
                               int64_t* bcast_need, K* pmask_out, bool early, int hb, K prefix0, K pmask0,
-                              int min_bit, Xf xf = Xf()) {
+                              int min_bit, Xf xf = Xf(), bool unique = false) {
+  constexpr uint32_t kFinish = 2 * kThreads * 4 / sizeof(K);  // keys that fit hist
   __shared__ int done;
+  __shared__ uint32_t bin_count, fin_n;
   const int t = threadIdx.x;
   K prefix = prefix0, pmask = pmask0;
   int64_t need = k;
@@ -415,6 +422,7 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
         if ((int64_t)e < need && (int64_t)(e + c[j]) >= need) {
           *bcast_prefix = prefix | ((K)(uint32_t)(255 - 4 * t - j) << lo);
           *bcast_need = need - (int64_t)e;
+          bin_count = c[j];
           if (early && (int64_t)(e + c[j]) == need) done = 1;
         }
         e += c[j];
@@ -426,6 +434,29 @@ __device__ K radix_select_kth(const K* keys, int64_t n, int64_t k, uint32_t* his
     need = *bcast_need;
     pmask |= (K)dmask << lo;
     if (done) break;  // block-uniform; set only before the barrier above
+    if (unique && lo > min_bit && bin_count <= kFinish && bin_count <= kThreads) {  // block-uniform
+      K* list = reinterpret_cast<K*>(hist);  // both count buffers are done with
+      if (t == 0) fin_n = 0;
+      __syncthreads();
+      for (int64_t i = t; i < n; i += kThreads) {
+        const K key = xf(keys[i]);
+        const bool in = (key & pmask) == prefix;
+        const uint32_t slot = wave_append(in, &fin_n);
+        if (in) list[slot] = key;
+      }
+      __syncthreads();
+      const uint32_t m = fin_n;  // == bin_count
+      if ((uint32_t)t < m) {
+        const K kt = list[t];
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < m; ++j) r += list[j] > kt ? 1u : 0u;
+        if ((int64_t)r == need - 1) *bcast_prefix = kt;
+      }
+      __syncthreads();
+      prefix = *bcast_prefix;
+      pmask = ~(K)0;
+      break;
+    }
     hb = lo;
     buf ^= 1;
   }
@@ -1795,7 +1826,7 @@ __device__ uint64_t select_top(const uint64_t* keys, int64_t n, int64_t k, int h
   const uint64_t pmask0 = hb >= 64 ? 0 : ~((((uint64_t)1) << hb) - 1);
   uint64_t pmask = 0;
   const uint64_t kth = radix_select_kth<uint64_t, Xf>(keys, n, k, hist, bprefix, bneed, &pmask, true, hb,
-                                                      prefix0 & pmask0, pmask0, 0, xf);
+                                                      prefix0 & pmask0, pmask0, 0, xf, true);
   if (threadIdx.x == 0) *nsel = 0;
   __syncthreads();
   for (int64_t i = threadIdx.x; i < n; i += kThreads) {
@@ -1829,37 +1860,35 @@ struct KeyCompress {
   }
 };
 
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 // The k best of n unique keys, written best first as row indices (and
-// scores) of query q. Each winner's place is the number of winners above
-// it: a wave takes 64 winners, one per lane, and compares each with every
-// winner, 64 at a time from registers (readlane), so the ordering costs
-// about k^2 / 16 wave instructions and no LDS traffic.
+// scores) of query q. Each winner's place is the number of winners above it,
+// counted by its own thread over broadcast LDS reads of the winners, two keys
+// per read and four independent counts (no sorting network, no barrier
+// between steps).
 template <int M, typename Xf = KeyIdentity>
 __device__ void select_and_write(const uint64_t* keys, int64_t n, int64_t q, const TopkArgs& a, int hb,
                                  uint64_t prefix0, uint64_t* sel, uint32_t* hist, uint64_t* bprefix, int64_t* bneed,
                                  uint32_t* nsel, Xf xf = Xf()) {
   uint64_t pmask;
   select_top<Xf>(keys, n, a.k, hb, prefix0, sel, hist, bprefix, bneed, nsel, &pmask, xf);
-  const int lane = threadIdx.x % kWave;
-  for (int wb = (threadIdx.x / kWave) * kWave; wb < a.k; wb += kThreads) {  // wave-uniform
-    const int w = wb + lane;
-    const uint64_t kw = w < a.k ? sel[w] : 0;
-    uint32_t r = 0;
-    for (int cb = 0; cb < a.k; cb += kWave) {
-      const uint64_t kc = cb + lane < a.k ? sel[cb + lane] : 0;  // 0 is below every key
-#pragma unroll
-      for (int j = 0; j < kWave; ++j) r += readlane64(kc, j) > kw ? 1u : 0u;
+  const int k = a.k;
+  const ulonglong2* s2 = reinterpret_cast<const ulonglong2*>(sel);  // sel is 16-byte aligned (LDS base)
+  for (int w = threadIdx.x; w < k; w += kThreads) {
+    const uint64_t kw = sel[w];
+    uint32_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+    int j = 0;
+#pragma unroll 4
+    for (; j + 4 <= k; j += 4) {
+      const ulonglong2 x = s2[j / 2], y = s2[j / 2 + 1];
+      r0 += x.x > kw ? 1u : 0u;
+      r1 += x.y > kw ? 1u : 0u;
+      r2 += y.x > kw ? 1u : 0u;
+      r3 += y.y > kw ? 1u : 0u;
     }
-    if (w < a.k) {
-      a.out_idx[q * a.k + r] = (int32_t)(~(uint32_t)kw);
-      if (a.out_score) a.out_score[q * a.k + r] = key_score<M>((uint32_t)(kw >> 32));
-    }
+    for (; j < k; ++j) r0 += sel[j] > kw ? 1u : 0u;
+    const uint32_t r = r0 + r1 + r2 + r3;
+    a.out_idx[q * a.k + r] = (int32_t)(~(uint32_t)kw);
+    if (a.out_score) a.out_score[q * a.k + r] = key_score<M>((uint32_t)(kw >> 32));
   }
   __syncthreads();
 }
