@@ -161,6 +161,32 @@ def test_large_candidate_sets_compact_in_place(N, lds_keys, nq, dev):
     assert_topk_equal(gi[sel], gs[sel], oi, osc)
 
 
+@pytest.mark.parametrize("mma", [True, False])
+def test_fallback_at_max_k_and_width(mma, dev):
+    """No candidate slots outside the sample sends every query with a scan
+    survivor to the whole-corpus fallback, here at the largest k (1,024) and
+    width (N = 65,536), where the fallback's LDS (the selected keys, a buffer
+    of k + 512 keys and the query's 1,024 words) is largest and the buffer is
+    cut back to its k best many times; 70 queries, so that the matrix-core
+    scan applies (or the vector scan, switched). The result must equal the
+    oracle's."""
+    from paper_1910_04658_amd import binding as bs
+    N = 65536
+    c = datagen.lognormal_corpus(3000, d=200_000, mean=400.0, sd=300.0, seed=31)
+    w, S = sketch_both(c, N, 12, dev)
+    q = np.linspace(0, 2999, 70).astype(np.int64)
+    try:
+        bs.debug_set_topk_mma(mma)
+        bs.debug_set_topk_limits(slab_capacity=0)
+        gi, gs = gpu_topk(w[q.tolist()].contiguous(), w, N, oracle.JS, 1024)
+    finally:
+        bs.debug_set_topk_limits()
+        bs.debug_set_topk_mma(True)
+    sel = np.arange(0, 70, 10)
+    oi, osc = oracle.topk(sets_rows(S, q[sel]), S, N, oracle.JS, 1024)
+    assert_topk_equal(gi[sel], gs[sel], oi, osc)
+
+
 def test_exact_ties_break_by_index(dev):
     """Many identical corpus rows: equal scores, ordered by smaller index."""
     base = datagen.small_corpus(n=50, d=4000, seed=24)
