@@ -16,7 +16,9 @@ durations come from a separate eager pass, from HIP events that the library
 records on the launching stream while timing is enabled.
 
 Printed: one JSON line (see the keys below). `value` is pair estimates per
-second of the whole step (sketching included).
+second of the whole step (sketching included). `vector_scan` repeats the step
+at the metric's width with the pair counts on the vector ALU (the matrix
+cores switched off) and gives that scan's int32 VALU roofline.
 """
 from __future__ import annotations
 
@@ -612,6 +614,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-problems run")
     ap.add_argument("--no-dense", action="store_true", help="skip the small-corpus all-pairs estimate run")
     ap.add_argument("--graph", action="store_true", help="time replays of the step recorded into a HIP graph")
+    ap.add_argument("--no-vector-scan", action="store_true",
+                    help="skip the extra run of the step with the pair counts on the vector ALU")
     ap.add_argument("--vector-scan", action="store_true",
                     help="count pairs on the vector ALU at every width (profiling the VALU scan; the default puts "
                          "widths that are multiples of 256 on the matrix cores)")
@@ -742,6 +746,26 @@ def main():
                                  "roofline": scan_roofline(N, ktN), "roofline_sketch": sketch_roofline(N, ktN)}
     if not args.no_mse:
         out["jaccard_mse"] = {str(N): jaccard_mse(results[N][0], corpus, queries) for N in widths}
+    if not args.vector_scan and not args.no_vector_scan and args.N % 256 == 0:
+        # the same step with the pair counts on the vector ALU (AND + popcount),
+        # for the int32 VALU roofline of the popcount path at the metric's width
+        from paper_1910_04658_amd import binding as bs
+        bs.debug_set_topk_mma(False)
+        try:
+            vstep = Step(dev_in, args.N, k, nC, nQ, dev)
+            vms, vkt = timed(vstep, 20, 3)
+        finally:
+            bs.debug_set_topk_mma(True)
+        S = bs.topk_sample_size(nC)
+        ops = nQ * (nC - S) * (args.N // 16)
+        t = vkt["topk_scan"]["avg_ms"] / 1e3
+        out["vector_scan"] = {
+            "N": args.N, "ms_per_step": vms, "pair_estimates_per_s": nQ * nC / (vms / 1e3),
+            "kernels_ms": {n: v["avg_ms"] for n, v in vkt.items()},
+            "roofline": {"bound": "alu", "achieved": ops / t / 1e12, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                         "frac": ops / t / 1e12 / PEAK_VALU_TOPS, "kernel": "topk_scan", "ops_per_launch": ops,
+                         "avg_launch_ms": vkt["topk_scan"]["avg_ms"]}}
+        log("vector scan: %s" % out["vector_scan"])
     if not args.no_dense:
         log("all-pairs estimates of the small corpus ...")
         out["dense_small_corpus"] = dense_eval(dev)
