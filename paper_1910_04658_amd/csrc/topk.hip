@@ -862,13 +862,17 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
 // m is clamped to [0, 65535]: lowering it only admits more candidates.
 constexpr int kBoundX = 16;  // table rows (x_c values) per block of the threshold kernel
 
-// m[x_c][q] of one query for the table rows xc[r] (r < R, xc[r] <= N + 1):
-// X = max{x in [0, N] : T(x) <= bound} (T non-decreasing), or -1, for the R
-// rows at once by a search whose steps depend only on N (so every row and
-// lane takes the same steps and every read is inside the table), each step
-// issuing one table read per row before using any. Row N + 1, and every row
-// of a query past the batch (q_ok false), is 65535: no count of N < 65536
-// reaches it.
+// m[x_c][q] of one query for the table rows xc[r] (r < R, xc[r] <= N + 1),
+// with X = max{x in [0, N] : T[x] <= bound} (T non-decreasing), or -1. X is
+// first estimated from the inverse of T(x) = ln(1 - x/N) / ln(1 - 1/N),
+// x <= N (1 - exp(bound ln(1 - 1/N))), then settled against the table itself,
+// which alone decides (so the estimate's rounding cannot change X): each
+// round reads T[X] and T[X + 1] and moves X one step down while T[X] > bound,
+// or up while T[X + 1] <= bound. The estimate is almost always exact or one
+// off; a wave with a row still moving after three rounds runs the search
+// below for all its rows (steps depending only on N, every read inside the
+// table). Row N + 1, and every row of a query past the batch (q_ok false),
+// is 65535: no count of N < 65536 reaches it.
 template <int M, int R>
 __device__ __forceinline__ void bound_rows(const float* lut, int32_t N, const QConst& k, bool q_ok, const int (&xc)[R],
                                            uint16_t (&m)[R]) {
@@ -880,28 +884,54 @@ __device__ __forceinline__ void bound_rows(const float* lut, int32_t N, const QC
     if (M == BS_COSINE) bound = fmaf(sqrtf(Tc), k.B, bound);
     bnd[r] = bound;
   }
-  int base[R];
+  const float L = log1pf(-1.0f / (float)N);  // < 0
+  int X[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) base[r] = 0;
-  for (int len = N + 1; len > 1;) {  // the count of x <= X lies in [base, base + len]
-    const int half = len >> 1;
-    float tv[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) tv[r] = lut[base[r] + half];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int r = 0; r < R; ++r) base[r] = tv[r] <= bnd[r] ? base[r] + half : base[r];
-    len -= half;
+  for (int r = 0; r < R; ++r) {
+    const float e = (float)N * (1.0f - __expf(bnd[r] * L));
+    X[r] = !(e >= 0.0f) ? -1 : (e >= (float)N ? N : (int)e);  // (a NaN bound starts at -1)
   }
-  float tv[R];
+  bool moving = true;
+  for (int round = 0; round < 4 && moving; ++round) {
+    float tx[R], tn[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) tv[r] = lut[base[r]];
+    for (int r = 0; r < R; ++r) {
+      tx[r] = lut[X[r] > 0 ? X[r] : 0];
+      tn[r] = lut[X[r] < N ? X[r] + 1 : N];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool down = X[r] >= 0 && !(tx[r] <= bnd[r]);
+      const bool up = X[r] < N && tn[r] <= bnd[r];
+      if (round < 3) X[r] += (up ? 1 : 0) - (down ? 1 : 0);
+      any = any || up || down;
+    }
+    moving = __ballot(any) != 0;  // wave-uniform
+  }
+  if (moving) {  // the search, for every row of the wave's lanes
+    int base[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) base[r] = 0;
+    for (int len = N + 1; len > 1;) {  // the count of x <= X lies in [base, base + len]
+      const int half = len >> 1;
+      float tv[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) tv[r] = lut[base[r] + half];
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int r = 0; r < R; ++r) base[r] = tv[r] <= bnd[r] ? base[r] + half : base[r];
+      len -= half;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) X[r] = base[r] + (lut[base[r]] <= bnd[r] ? 1 : 0) - 1;
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     m[r] = 65535;
     if (q_ok && xc[r] <= N) {
-      const int X = base[r] + (tv[r] <= bnd[r] ? 1 : 0) - 1;
-      const int64_t mm = (int64_t)k.xq + xc[r] - X;
+      const int64_t mm = (int64_t)k.xq + xc[r] - X[r];
       m[r] = (uint16_t)(mm < 0 ? 0 : (mm > 65535 ? 65535 : mm));
     }
   }
