@@ -860,7 +860,10 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
 // non-decreasing that means x_u <= X = max{x : T(x) <= bound}, i.e.
 //   x_ab >= m[x_c][q] = x_q + x_c - X.
 // m is clamped to [0, 65535]: lowering it only admits more candidates.
-constexpr int kBoundX = 16;  // table rows (x_c values) per block of the threshold kernel
+// Table rows (x_c values) per block of the threshold kernel: 16, or 64 from
+// N = 2048 on, where each block's copy of T (4 (N + 1) bytes) would
+// otherwise outweigh its work.
+__host__ __device__ constexpr int bound_rows_per_block(int32_t N) { return N >= 2048 ? 64 : 16; }
 
 // m[x_c][q] of one query for the table rows xc[r] (r < R, xc[r] <= N + 1),
 // with X = max{x in [0, N] : T[x] <= bound} (T non-decreasing), or -1. X is
@@ -937,7 +940,7 @@ __device__ __forceinline__ void bound_rows(const float* lut, int32_t N, const QC
   }
 }
 
-template <int M, bool LDS_LUT>
+template <int M, bool LDS_LUT, int BX>
 __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_t by) {
   extern __shared__ float lut_s[];
   const float* lut = a.t32;
@@ -952,19 +955,19 @@ __device__ __forceinline__ void bound_body(const TopkArgs& a, int64_t bx, int64_
   const bool q_ok = qi < a.nQ;
   if (q_ok) k = a.qc[qi];
   constexpr int RW = kThreads / kWave;
-  constexpr int RPT = kBoundX / RW;  // table rows per thread
+  constexpr int RPT = BX / RW;  // table rows per thread
   const int wid = threadIdx.x / kWave;
   int xc[RPT];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int x = (int)by * kBoundX + wid + r * RW;
+    const int x = (int)by * BX + wid + r * RW;
     xc[r] = x <= a.N + 1 ? x : a.N + 1;
   }
   uint16_t m[RPT];
   bound_rows<M, RPT>(lut, a.N, k, q_ok, xc, m);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int x = (int)by * kBoundX + wid + r * RW;
+    const int x = (int)by * BX + wid + r * RW;
     if (x <= a.N + 1) a.mtab[(size_t)x * a.nQp + qi] = m[r];
   }
 }
@@ -2236,9 +2239,9 @@ template <bool ONE, int M>
 __global__ __launch_bounds__(kThreads) void topk_sample_select_kernel(GroupArgs g) {
   BS_GROUP_LOOP((sample_select_body<M>(a, lb)))
 }
-template <bool ONE, int M, bool LDS_LUT>
+template <bool ONE, int M, bool LDS_LUT, int BX>
 __global__ __launch_bounds__(kThreads) void topk_bound_kernel(GroupArgs g) {
-  BS_GROUP_LOOP((bound_body<M, LDS_LUT>(a, lb % (a.nQp / kWave), lb / (a.nQp / kWave))))
+  BS_GROUP_LOOP((bound_body<M, LDS_LUT, BX>(a, lb % (a.nQp / kWave), lb / (a.nQp / kWave))))
 }
 template <bool ONE, int W32T, int QPL>
 __global__ __launch_bounds__(kThreads) void topk_scan_kernel(GroupArgs g) {
@@ -2279,7 +2282,10 @@ int64_t stage_blocks(const TopkArgs& a, int st) {
   switch (st) {
     case kStSample: return a.s_rblocks * a.s_nqb;
     case kStSampleSelect: return a.nQ;
-    case kStBound: return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 2 + kBoundX - 1) / kBoundX) : 0;
+    case kStBound: {
+      const int bx = bound_rows_per_block(a.N);
+      return (scan && !a.rows) ? (a.nQp / kWave) * ((a.N + 2 + bx - 1) / bx) : 0;
+    }
     case kStScan:
       if (!scan) return 0;
       if (a.rows) return (a.n_slabs + kThreads / kWave - 1) / (kThreads / kWave);
@@ -2344,7 +2350,10 @@ const void* stage_kernel(const TopkArgs& a, int st) {
       }
 #undef BS_SAMPLE
     case kStSampleSelect: return (const void*)topk_sample_select_kernel<ONE, M>;
-    case kStBound: return lds_lut ? (const void*)topk_bound_kernel<ONE, M, true> : (const void*)topk_bound_kernel<ONE, M, false>;
+    case kStBound:
+      if (bound_rows_per_block(a.N) == 64)
+        return lds_lut ? (const void*)topk_bound_kernel<ONE, M, true, 64> : (const void*)topk_bound_kernel<ONE, M, false, 64>;
+      return lds_lut ? (const void*)topk_bound_kernel<ONE, M, true, 16> : (const void*)topk_bound_kernel<ONE, M, false, 16>;
     case kStScan:
       if (a.rows) {
         switch (W32) {
