@@ -92,6 +92,7 @@ def ingest_counters(fetch_dir, write_dir, copy_bytes, N):
         return out
 
     res = {}
+    seen = {}  # short name -> the full kernel names counted under it
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         k = per_kernel(d, counter)
         copy = [v for name, vals in k.items() if "copy" in name.lower() or "elementwise" in name.lower()
@@ -102,7 +103,12 @@ def ingest_counters(fetch_dir, write_dir, copy_bytes, N):
         for name, vals in k.items():
             for short in KERNEL_SOURCES:
                 if short + "_" in name or short + "_lds" in name or name.split("(")[0].endswith(short + "_kernel"):
+                    seen.setdefault(short, set()).add(name)
                     res.setdefault(short, {})[counter] = (sum(vals) / len(vals), factor, len(vals))
+    for short, names in seen.items():
+        if len(names) > 1:  # one figure per kernel: a run that mixes variants cannot be ingested
+            raise SystemExit("%s: %d kernel variants in the counter run (%s); profile one variant, e.g. with "
+                             "--no-vector-scan" % (short, len(names), "; ".join(sorted(n[:80] for n in names))))
     out = {}
     for short, c in res.items():
         if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
