@@ -71,7 +71,7 @@ constexpr int kFbRowsPerThread = 2; // corpus rows per thread per step of the wh
 constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
 constexpr int kMmaWaves = 16384;      // waves of the matrix-core scan grid, about
 constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
-constexpr int kMmaQCap = 256;         // survivor queue entries per wave of the matrix-core scan
+constexpr int kMmaQCap = 512;         // survivor queue entries per wave of the matrix-core scan
 constexpr int kMmaHoldChunks = 2;     // the matrix-core scan holds a group's query words in registers up to this many chunks
 
 __host__ __device__ constexpr int64_t round_up64(int64_t x) { return (x + 63) / 64 * 64; }
@@ -1307,6 +1307,13 @@ __device__ __forceinline__ uint64_t make_key(float sc, uint32_t idx) {
 typedef int bs_v8i __attribute__((ext_vector_type(8)));
 typedef float bs_v16f __attribute__((ext_vector_type(16)));
 
+// The scan's accumulators start at 2^23 instead of 0. Every partial sum is
+// then an integer in [2^23, 2^24), exact in FP32, and its bit pattern is
+// 0x4B000000 + the count: the epilogue compares the count with its bound as
+// an integer (the low 16 bits for N < 65536), with no conversion per pair.
+constexpr float kCountBias = 8388608.0f;
+constexpr uint32_t kCountBiasBits = 0x4B000000u;
+
 template <int D>
 __device__ __forceinline__ bs_v8i fp4_class(const uint32_t (&w)[4]) {
   bs_v8i r = {0, 0, 0, 0, 0, 0, 0, 0};  // FP4 operands use the low four words
@@ -1541,7 +1548,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
 #pragma unroll
       for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[ct][qt][e] = 0.0f;
+        for (int e = 0; e < 16; ++e) acc[ct][qt][e] = kCountBias;
     constexpr int KU = HOLD ? KCT : 1;
 #pragma unroll KU
     for (int ch = 0; ch < KC; ++ch) {
@@ -1552,6 +1559,10 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
       uint32_t qn4[2][4], cn[2][4];
       if constexpr (!HOLD) load_a(nch, qn4);
       load_b(nt, nch, cn);
+      // keep the next step's loads ahead of this step's products (left to
+      // itself the scheduler sinks them to the end of the step, and the
+      // next step then waits for their whole round trip)
+      __builtin_amdgcn_sched_barrier(0);
       auto klass = [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         bs_v8i A[2];
@@ -1615,20 +1626,27 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
           }
   #pragma unroll
           for (int e = 0; e < 16; ++e) {
-            if (e % 4 == 0) __builtin_amdgcn_sched_barrier(0);  // four queries at a time: short live ranges
+            if (e % 4 == 0) {
+              __builtin_amdgcn_sched_barrier(0);  // four queries at a time: short live ranges
+              // room for four full ballots (one check per four queries keeps
+              // the drain's code out of every query's path)
+              if (qn > (uint32_t)(kMmaQCap - 4 * kWave)) drain();
+            }
             const uint4 m4 = mg[e / 8];
             const uint32_t mw32 = (e % 8) / 2 == 0 ? m4.x : (e % 8) / 2 == 1 ? m4.y : (e % 8) / 2 == 2 ? m4.z : m4.w;
-            const float m = (float)(e % 2 == 0 ? (mw32 & 0xffffu) : (mw32 >> 16));
-            // counts and bounds are exact integers in FP32
-            const bool pass = acc[ct][qt][e] >= m;
+            const uint32_t m = e % 2 == 0 ? (mw32 & 0xffffu) : (mw32 >> 16);
+            // the accumulator's bits are 0x4B000000 + x_ab (x_ab < 2^16 for
+            // N < 65536: its low half)
+            const uint32_t bits = __float_as_uint(acc[ct][qt][e]);
+            const uint32_t x = EM ? bits - kCountBiasBits : (bits & 0xffffu);
+            const bool pass = x >= m;
             uint64_t bal = __builtin_amdgcn_ballot_w64(pass);
             if (EM) bal &= rowm & qvalid(qt, e);
             if (bal) {  // wave-uniform
-              if (qn > (uint32_t)(kMmaQCap - kWave)) drain();
               const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)bal, qn));
               if (EM ? ((bal >> lane) & 1) != 0 : pass) {
-                squeue[pos] = ((uint64_t)(hi_t | (uint32_t)acc[ct][qt][e]) << 32) | r;
+                squeue[pos] = ((uint64_t)(hi_t | x) << 32) | r;
                 squery[pos] = (uint8_t)(qbase_t + 32 * qt + e);
               }
               qn += (uint32_t)__popcll(bal);
