@@ -72,6 +72,7 @@ constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-
 constexpr int kMmaWaves = 16384;      // waves of the matrix-core scan grid, about
 constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
 constexpr int kMmaQCap = 512;         // survivor queue entries per wave of the matrix-core scan
+constexpr int kMmaSlabRowBits = 26;   // a matrix-core scan slab holds fewer than 2^26 rows
 constexpr int kMmaHoldChunks = 2;     // the matrix-core scan holds a group's query words in registers up to this many chunks
 
 __host__ __device__ constexpr int64_t round_up64(int64_t x) { return (x + 63) / 64 * 64; }
@@ -160,6 +161,9 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
     if (n_slabs > kMaxSlabs) n_slabs = kMaxSlabs;
     if (n_slabs < 1) n_slabs = 1;
     const int64_t tiles = (nC + kMmaRows - 1) / kMmaRows;
+    // survivor entries keep a row as its offset in the slab, in 26 bits
+    const int64_t tiles_max = ((int64_t)1 << kMmaSlabRowBits) / kMmaRows;
+    if ((tiles + n_slabs - 1) / n_slabs > tiles_max) n_slabs = (tiles + tiles_max - 1) / tiles_max;
     p.slab = (tiles + n_slabs - 1) / n_slabs * kMmaRows;  // whole wave tiles
   } else if (p.split) {
     p.ngrp = nqb;
@@ -1438,19 +1442,18 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   const uint32_t s_end = (uint32_t)s_end64;
   // first sampled row at or after the slab start (rows past s_end are never sampled)
   uint32_t next_s = (uint32_t)((c_begin + a.stride - 1) / a.stride * a.stride);
-  // Survivors are first appended to the wave's LDS queue as finished
-  // entries, each with its query (a byte beside it), at positions from a
-  // ballot prefix count (one queue head for the wave). The queue is drained
+  // Survivors are first appended to the wave's LDS queue as entries whose
+  // low word holds the query (of the group) in its top six bits and the
+  // row's offset in the slab below them (slabs are under 2^26 rows), at
+  // positions from a ballot prefix count (one queue head for the wave). The queue is drained
   // when nearly full and once at the end of the slab: an LDS atomic on the
   // query's counter gives each entry its slot s, stored at
   // cands[q * kmax + S + s * n_slabs + sl]. Slot order within a query does
   // not matter (the select orders candidates by their keys). Draining rarely
   // keeps global stores, and the waits on them, out of the tile loop.
   __shared__ uint64_t sq_lds[kThreads / kWave][kMmaQCap];
-  __shared__ uint8_t sqq_lds[kThreads / kWave][kMmaQCap];
   __shared__ uint32_t sc_lds[kThreads / kWave][kWave];
   uint64_t* const squeue = sq_lds[wid];
-  uint8_t* const squery = sqq_lds[wid];
   uint32_t* const scount = sc_lds[wid];
   scount[lane] = 0u;
   uint64_t* const cbase = a.cands + (size_t)(qg * kWave) * a.kmax + a.S + sl;
@@ -1464,9 +1467,11 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
     for (uint32_t b = 0; b < qn; b += kWave) {
       if (b + (uint32_t)lane < qn) {
         const uint64_t e = squeue[b + lane];
-        const uint32_t qid = squery[b + lane];
+        const uint32_t lo = (uint32_t)e;
+        const uint32_t qid = lo >> kMmaSlabRowBits;
+        const uint32_t row = (uint32_t)c_begin + (lo & ((1u << kMmaSlabRowBits) - 1u));
         const uint32_t slot = atomicAdd(&scount[qid], 1u);
-        if (slot < scap) cbase[(size_t)qid * a.kmax + (size_t)slot * nsl] = e;
+        if (slot < scap) cbase[(size_t)qid * a.kmax + (size_t)slot * nsl] = (e & 0xFFFFFFFF00000000ull) | row;
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1602,15 +1607,15 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   #pragma unroll
       for (int ct = 0; ct < 2; ++ct) {
         const uint32_t R = 32u * ct + c;
-        const uint32_t r = r0 + R;
         const uint64_t rowm = EM ? __builtin_amdgcn_ballot_w64(row_ok[ct]) : ~0ull;
-        // entry of a survivor (raw_entry): high word x_c << 16 | x_ab (x_ab
-        // alone at N = 65536), low word the row; its query 16 h + 32 qt + e
+        // queue entry of a survivor: high word as in raw_entry, x_c << 16 |
+        // x_ab (x_ab alone at N = 65536); low word its query 16 h + 32 qt + e
+        // of the group above the row's offset in the slab
         uint32_t hi_t = a.N < 65536 ? (uint32_t)xcur[ct] << 16 : 0u;
-        uint32_t qbase_t = 16u * h;
+        uint32_t lo_t = ((uint32_t)tile * kMmaRows + R) | (16u * h) << kMmaSlabRowBits;
         // formed anew per tile: hoisted out of the tile loop, the per-query
         // values would take 64 registers
-        asm volatile("" : "+v"(qbase_t), "+v"(hi_t));
+        asm volatile("" : "+v"(lo_t), "+v"(hi_t));
   #pragma unroll
         for (int qt = 0; qt < 2; ++qt) {
           // bounds of queries 32 qt + 16 h .. + 15 for this row: pieces 4 qt + 2 h and + 1
@@ -1644,11 +1649,9 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
             if (EM) bal &= rowm & qvalid(qt, e);
             if (bal) {  // wave-uniform
               const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, qn));
-              if (EM ? ((bal >> lane) & 1) != 0 : pass) {
-                squeue[pos] = ((uint64_t)(hi_t | x) << 32) | r;
-                squery[pos] = (uint8_t)(qbase_t + 32 * qt + e);
-              }
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+              if (EM ? ((bal >> lane) & 1) != 0 : pass)
+                (squeue + qn)[pos] = ((uint64_t)(hi_t | x) << 32) | (lo_t + ((uint32_t)(32 * qt + e) << kMmaSlabRowBits));
               qn += (uint32_t)__popcll(bal);
             }
           }
