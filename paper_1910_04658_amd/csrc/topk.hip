@@ -1382,22 +1382,34 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
     q = q < a.nQ ? q : a.nQ - 1;
     qoff[qt] = (uint32_t)(q - qg * kWave) * rowb + 16u * h;
   }
+  // every operand address is a uniform base (scalar registers) plus a lane
+  // offset below 64 rows, so a step forms no address on the vector ALU
   auto load_a = [&](int ch, uint32_t (&qa)[2][4]) {
+    const char* qb = qbase + 32u * (uint32_t)ch;
 #pragma unroll
     for (int qt = 0; qt < 2; ++qt) {
-      const uint4 v = *reinterpret_cast<const uint4*>(qbase + (qoff[qt] + 32u * ch));
+      const uint4 v = *reinterpret_cast<const uint4*>(qb + qoff[qt]);
       qa[qt][0] = v.x;
       qa[qt][1] = v.y;
       qa[qt][2] = v.z;
       qa[qt][3] = v.w;
     }
   };
-  auto load_b = [&](int32_t tile, int ch, uint32_t (&cb)[2][4]) {
+  auto tile_base = [&](int32_t tile) { return cslab + (size_t)(uint32_t)tile * kMmaRows * rowb; };
+  // B lane offsets in a tile: row 32 ct + c (past the slab: its last row)
+  auto tile_off = [&](int32_t tile, uint32_t (&bo)[2]) {
+    const uint32_t left = nrows - (uint32_t)tile * kMmaRows;  // >= 1: tile < ntiles
 #pragma unroll
     for (int ct = 0; ct < 2; ++ct) {
-      uint32_t r = (uint32_t)tile * kMmaRows + 32u * ct + c;
-      r = r < nrows ? r : nrows - 1;
-      const uint4 v = *reinterpret_cast<const uint4*>(cslab + (r * rowb + 16u * h + 32u * ch));
+      const uint32_t r = 32u * ct + c;
+      bo[ct] = (r < left ? r : left - 1) * rowb + 16u * h;
+    }
+  };
+  auto load_b = [&](const char* tb, int ch, const uint32_t (&bo)[2], uint32_t (&cb)[2][4]) {
+    const char* bb = tb + 32u * (uint32_t)ch;
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const uint4 v = *reinterpret_cast<const uint4*>(bb + bo[ct]);
       cb[ct][0] = v.x;
       cb[ct][1] = v.y;
       cb[ct][2] = v.z;
@@ -1503,16 +1515,21 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   }
   uint32_t qa[2][4], cb[2][4];
   if constexpr (!HOLD) load_a(0, qa);
-  load_b(0, 0, cb);
+  uint32_t boff[2];
+  tile_off(0, boff);
+  load_b(tile_base(0), 0, boff, cb);
   int32_t xc[2];
   load_xc(0, xc);
   // With four or more chunks a tile is long enough to hide the copy of its
-  // bounds. The epilogue waits for the copy with vmcnt(VM_AFTER): the vector
-  // memory operations issued after it are the operand loads of the tile's
-  // chunk steps (two per step, four without held query words), and they
-  // complete in order. Width-generic code (KCT = 0) waits for everything.
+  // bounds, issued by the first step after its operand loads. The epilogue
+  // waits for the copy with vmcnt(VM_AFTER): the vector memory operations
+  // issued after it are the operand loads of the later steps (two per step,
+  // four without held query words), and they complete in order (each step
+  // also waits for all earlier loads before issuing its own, which covers
+  // the copy from the second step on). Width-generic code (KCT = 0) waits
+  // for everything.
   constexpr bool LDSB = KCT == 0 || KCT >= 4;
-  constexpr int VM_AFTER0 = KCT * (HOLD ? 2 : 4);
+  constexpr int VM_AFTER0 = (KCT > 0 ? KCT - 1 : 0) * (HOLD ? 2 : 4);
   constexpr int VM_AFTER = VM_AFTER0 > 63 ? 63 : VM_AFTER0;
   constexpr int VM_WAIT = (VM_AFTER & 0xF) | ((VM_AFTER >> 4) << 14) | (0x7 << 4) | (0xF << 8);
   for (int32_t tile = 0; tile < ntiles; ++tile) {
@@ -1534,12 +1551,10 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
       row_ok[ct] = r0 + R < r_hi && !((smask >> R) & 1);
       xb[ct] = row_ok[ct] ? xc[ct] : xskip;
     }
-    if constexpr (LDSB) {
-      // the previous epilogue's reads of the region are done (their values
-      // were used); then this tile's bounds start their way into it
-      __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-      bounds_to_lds(xb);
-    }
+    // the previous epilogue's reads of the bounds region are done (their
+    // values were used); the first step then starts this tile's bounds on
+    // their way into it
+    if constexpr (LDSB) __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
     if constexpr (HOLD) {  // class operands formed anew per tile (hoisted, they would take 32 registers per chunk)
 #pragma unroll
       for (int ch = 0; ch < (HOLD ? KCT : 1); ++ch)
@@ -1554,16 +1569,23 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
       for (int qt = 0; qt < 2; ++qt)
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[ct][qt][e] = kCountBias;
-    constexpr int KU = HOLD ? KCT : 1;
-#pragma unroll KU
-    for (int ch = 0; ch < KC; ++ch) {
-      // next step (the last step reloads itself: in bounds, unused)
-      const bool last = ch + 1 == KC;
-      const int32_t nt = last ? (tile + 1 < ntiles ? tile + 1 : tile) : tile;
-      const int nch = last ? (tile + 1 < ntiles ? 0 : ch) : ch + 1;
+    // the last step loads the next tile's first chunk (the last tile's last
+    // step reloads itself: in bounds, unused)
+    const char* const tb = tile_base(tile);
+    const bool more = tile + 1 < ntiles;
+    const char* const tbn = more ? tile_base(tile + 1) : tb;
+    uint32_t boffn[2];
+    tile_off(more ? tile + 1 : tile, boffn);
+    auto step = [&](int ch, const char* nb, int nch, const uint32_t (&nbo)[2], bool first) {
       uint32_t qn4[2][4], cn[2][4];
+      // The step's operands (loaded during the previous step) are complete
+      // before the next ones are issued: without this wait the compiler
+      // waits for everything, the loads just issued included, at the step's
+      // first use of its operands.
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
       if constexpr (!HOLD) load_a(nch, qn4);
-      load_b(nt, nch, cn);
+      load_b(nb, nch, nbo, cn);
+      if (LDSB && first) bounds_to_lds(xb);
       // keep the next step's loads ahead of this step's products (left to
       // itself the scheduler sinks them to the end of the step, and the
       // next step then waits for their whole round trip)
@@ -1591,7 +1613,13 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
           if constexpr (!HOLD) qa[u][w] = qn4[u][w];
           cb[u][w] = cn[u][w];
         }
-    }
+    };
+    constexpr int KU = HOLD ? KCT : 1;
+#pragma unroll KU
+    for (int ch = 0; ch + 1 < KC; ++ch) step(ch, tb, ch + 1, boff, ch == 0);
+    step(KC - 1, tbn, more ? 0 : KC - 1, boffn, KC == 1);
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) boff[ct] = boffn[ct];
     if constexpr (LDSB) {
       if constexpr (KCT > 0) __builtin_amdgcn_s_waitcnt(VM_WAIT);  // this tile's bounds are in LDS
       else __builtin_amdgcn_s_waitcnt(0x0F70);                     // vmcnt(0)
