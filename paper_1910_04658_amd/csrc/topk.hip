@@ -69,7 +69,10 @@ constexpr int kSplitGridWaves = 32768; // waves of the word-split scan grid, abo
 constexpr int kSplitRows = 16;       // rows per partial-count exchange of the word-split scan
 constexpr int kFbRowsPerThread = 2; // corpus rows per thread per step of the whole-corpus fallback
 constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-core scan
-constexpr int kMmaWaves = 16384;      // waves of the matrix-core scan grid, about
+// waves of the matrix-core scan grid, about: two rounds of the 3,072 that
+// are resident at once (3 blocks of 4 waves on each of 256 CUs), so each wave
+// runs several tiles and its set-up and final drain are amortised
+constexpr int kMmaWaves = 6144;
 constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
 constexpr int kMmaQCap = 512;         // survivor queue entries per wave of the matrix-core scan
 constexpr int kMmaSlabRowBits = 26;   // a matrix-core scan slab holds fewer than 2^26 rows
