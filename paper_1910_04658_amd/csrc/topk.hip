@@ -75,7 +75,7 @@ constexpr int kMmaRows = 64;         // corpus rows per wave tile of the matrix-
 constexpr int kMmaWaves = 6144;
 constexpr int kXcds = 8;              // accelerator complex dies, one L2 each
 constexpr int kMmaQCap = 512;         // survivor queue entries per wave of the matrix-core scan
-constexpr int kMmaSlabRowBits = 26;   // a matrix-core scan slab holds fewer than 2^26 rows
+constexpr int kMmaSlabRowBits = 26;   // a matrix-core scan slab holds at most 2^26 rows (offsets fit 26 bits)
 constexpr int kMmaHoldChunks = 2;     // the matrix-core scan holds a group's query words in registers up to this many chunks
 
 __host__ __device__ constexpr int64_t round_up64(int64_t x) { return (x + 63) / 64 * 64; }
@@ -1459,7 +1459,7 @@ __device__ __forceinline__ void scan_mma_body(const TopkArgs& a, int64_t vbid) {
   uint32_t next_s = (uint32_t)((c_begin + a.stride - 1) / a.stride * a.stride);
   // Survivors are first appended to the wave's LDS queue as entries whose
   // low word holds the query (of the group) in its top six bits and the
-  // row's offset in the slab below them (slabs are under 2^26 rows), at
+  // row's offset in the slab below them (a slab holds at most 2^26 rows), at
   // positions from a ballot prefix count (one queue head for the wave). The queue is drained
   // when nearly full and once at the end of the slab: an LDS atomic on the
   // query's counter gives each entry its slot s, stored at

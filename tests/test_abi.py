@@ -165,6 +165,12 @@ def test_topk_plans_for_every_width_and_batch_size(lib):
                     for nC in (1, 100, 5000, 100_000):
                         k = min(10, nC)
                         assert lib.bs_topk_workspace_size(nQ, nC, N, k) > 0, (on, N, nQ, nC)
+            # a batch large enough that the matrix-core scan would run one
+            # slab per query group: the plan splits the corpus into slabs of
+            # at most 2^26 rows (survivor entries keep a row's offset in
+            # its slab in 26 bits)
+            for N in (256, 1024):
+                assert lib.bs_topk_workspace_size(400_000, 1 << 27, N, 10) > 0, (on, N)
         finally:
             lib.bs_debug_set_topk_mma(1)
     for N in widths:
