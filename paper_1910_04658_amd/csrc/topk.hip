@@ -803,9 +803,82 @@ __device__ __forceinline__ void sample_split_body(const TopkArgs& a, int64_t bx,
   }
 }
 
-// 1b. Per query: a lower bound tau on the k-th best sample key (LDS radix
-// select), the sample rows scoring at least tau, and the per-query constants
-// of the scan filter.
+// Compare-exchange into descending order, and Batcher's odd-even merge
+// sorting networks for 4 and 8 keys in registers.
+__device__ __forceinline__ void cx_desc(uint32_t& x, uint32_t& y) {
+  const uint32_t hi = x > y ? x : y, lo = x > y ? y : x;
+  x = hi;
+  y = lo;
+}
+__device__ __forceinline__ void sort4_desc(uint32_t (&v)[4]) {
+  cx_desc(v[0], v[1]); cx_desc(v[2], v[3]); cx_desc(v[0], v[2]); cx_desc(v[1], v[3]); cx_desc(v[1], v[2]);
+}
+__device__ __forceinline__ void sort8_desc(uint32_t (&v)[8]) {
+  cx_desc(v[0], v[1]); cx_desc(v[2], v[3]); cx_desc(v[4], v[5]); cx_desc(v[6], v[7]);
+  cx_desc(v[0], v[2]); cx_desc(v[1], v[3]); cx_desc(v[4], v[6]); cx_desc(v[5], v[7]);
+  cx_desc(v[1], v[2]); cx_desc(v[5], v[6]);
+  cx_desc(v[0], v[4]); cx_desc(v[1], v[5]); cx_desc(v[2], v[6]); cx_desc(v[3], v[7]);
+  cx_desc(v[2], v[4]); cx_desc(v[3], v[5]);
+  cx_desc(v[1], v[2]); cx_desc(v[3], v[4]); cx_desc(v[5], v[6]);
+}
+
+// The kt-th largest of S <= 2,048 keys in LDS (kt <= 64), exactly. Each wave
+// takes 512 keys (8 per lane, sorted in registers) and pops its kt largest
+// one at a time: the wave maximum of the lanes' heads, after which the lowest
+// lane holding it drops its head. Wave 0 then pops the kt largest of the four
+// waves' lists the same way (the kt largest overall are among them). Keys past
+// S read as 0, the smallest key, which cannot change the kt-th largest of
+// S >= kt keys. scratch: 4 x 64 words of LDS; *out: one LDS word.
+constexpr int kSmallKthKeys = 8 * kThreads;
+__device__ __forceinline__ uint32_t small_kth(const uint32_t* keys, int S, int kt, uint32_t* scratch, uint32_t* out) {
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  uint32_t v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int i = w * 8 * kWave + j * kWave + lane;
+    v[j] = i < S ? keys[i] : 0u;
+  }
+  sort8_desc(v);
+  uint32_t mine = 0;  // lane r: the wave's (r + 1)-th largest
+  for (int r = 0; r < kt; ++r) {
+    const uint32_t m = wave_max_u32(v[0]);
+    const int src = __builtin_ctzll(__ballot(v[0] == m));  // some lane holds m
+    if (lane == src) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) v[j] = v[j + 1];
+      v[7] = 0u;
+    }
+    if (lane == r) mine = m;
+  }
+  scratch[w * kWave + lane] = lane < kt ? mine : 0u;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t c[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[j] = scratch[j * kWave + lane];
+    sort4_desc(c);
+    uint32_t tau = 0;
+    for (int r = 0; r < kt; ++r) {
+      const uint32_t m = wave_max_u32(c[0]);
+      const int src = __builtin_ctzll(__ballot(c[0] == m));
+      if (lane == src) {
+        c[0] = c[1];
+        c[1] = c[2];
+        c[2] = c[3];
+        c[3] = 0u;
+      }
+      tau = m;
+    }
+    if (lane == 0) *out = tau;
+  }
+  __syncthreads();
+  return *out;
+}
+
+// 1b. Per query: a lower bound tau on the k-th best sample key (the kt-th
+// best sample key itself for samples of at most 2,048 rows and kt <= 64, else
+// an LDS radix select), the sample rows scoring at least tau, and the
+// per-query constants of the scan filter.
 template <int M>
 __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint32_t keys[];  // [S rounded up to 64]
@@ -821,30 +894,35 @@ __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q)
     kmax_s = 0;
   }
   __syncthreads();
-  // tau: the k-th best sample key resolved to the 16 bits below the highest
-  // bit where the keys differ. The lower edge of its bin is a lower bound on
-  // it, which is all the filter needs: every row scoring at least tau becomes
-  // a candidate, and the final selection is exact.
-  uint32_t mn = ~0u, mx = 0;
-  for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
-    const uint32_t key = keys[i];
-    mn = key < mn ? key : mn;
-    mx = key > mx ? key : mx;
-  }
-  mn = wave_min_u32(mn);
-  mx = wave_max_u32(mx);
-  if (threadIdx.x % kWave == 0) {
-    atomicMin(&kmin_s, mn);
-    atomicMax(&kmax_s, mx);
-  }
-  __syncthreads();
-  const uint32_t klo = kmin_s, khi = kmax_s;
   const float Tq = a.t32[xq];  // (used at the end: its load overlaps the selection)
-  const uint32_t diff = klo ^ khi;
-  const int hb = diff ? 32 - __clz((int)diff) : 0;
-  const uint32_t pmask0 = hb >= 32 ? 0u : ~((1u << hb) - 1u);
-  const uint32_t tau_key = radix_select_kth<uint32_t>(keys, a.S, a.kt, hist, &bprefix, &bneed, nullptr, true, hb,
-                                                      (uint32_t)khi & pmask0, pmask0, hb > 16 ? hb - 16 : 0);
+  uint32_t tau_key;
+  if (a.S <= kSmallKthKeys && a.kt <= kWave) {
+    tau_key = small_kth(keys, (int)a.S, (int)a.kt, hist, &kmin_s);
+  } else {
+    // tau: the kt-th best sample key resolved to the 16 bits below the highest
+    // bit where the keys differ. The lower edge of its bin is a lower bound on
+    // it, which is all the filter needs: every row scoring at least tau becomes
+    // a candidate, and the final selection is exact.
+    uint32_t mn = ~0u, mx = 0;
+    for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
+      const uint32_t key = keys[i];
+      mn = key < mn ? key : mn;
+      mx = key > mx ? key : mx;
+    }
+    mn = wave_min_u32(mn);
+    mx = wave_max_u32(mx);
+    if (threadIdx.x % kWave == 0) {
+      atomicMin(&kmin_s, mn);
+      atomicMax(&kmax_s, mx);
+    }
+    __syncthreads();
+    const uint32_t klo = kmin_s, khi = kmax_s;
+    const uint32_t diff = klo ^ khi;
+    const int hb = diff ? 32 - __clz((int)diff) : 0;
+    const uint32_t pmask0 = hb >= 32 ? 0u : ~((1u << hb) - 1u);
+    tau_key = radix_select_kth<uint32_t>(keys, a.S, a.kt, hist, &bprefix, &bneed, nullptr, true, hb,
+                                         (uint32_t)khi & pmask0, pmask0, hb > 16 ? hb - 16 : 0);
+  }
   uint64_t* cq = a.cands + (size_t)q * a.kmax;
   for (int64_t i = threadIdx.x; i < a.S; i += kThreads) {
     const bool win = keys[i] >= tau_key;
