@@ -158,7 +158,10 @@ Plan make_plan(int64_t nQ, int64_t nC, int32_t N, int32_t k, const TopkTune& tun
   if (p.mma) {
     p.ngrp = nqb;
     p.nqb4 = (nqb + 3) / 4;  // a block: four 64-query groups x one slab
-    const int64_t waves = tune.waves > 0 ? tune.waves : kMmaWaves;
+    // one round of resident waves for rows of one 256-bit chunk, whose tiles
+    // are short enough that a second round's ramp costs more than the balance
+    // it buys; two rounds otherwise
+    const int64_t waves = tune.waves > 0 ? tune.waves : (W32 <= 8 ? kMmaWaves / 2 : kMmaWaves);
     const int64_t per = 4 * (p.nqb4 > 0 ? p.nqb4 : 1);  // waves per slab (a batch may hold no queries)
     int64_t n_slabs = (waves + per - 1) / per;
     if (n_slabs > kMaxSlabs) n_slabs = kMaxSlabs;
@@ -875,10 +878,10 @@ __device__ __forceinline__ uint32_t small_kth(const uint32_t* keys, int S, int k
   return *out;
 }
 
-// 1b. Per query: a lower bound tau on the k-th best sample key (the kt-th
-// best sample key itself for samples of at most 2,048 rows and kt <= 64, else
-// an LDS radix select), the sample rows scoring at least tau, and the
-// per-query constants of the scan filter.
+// 1b. Per query: tau, the kt-th best sample key (exactly, in registers, for
+// samples of at most 2,048 rows and kt <= 64; else a lower bound on it from an
+// LDS radix select), the sample rows scoring at least tau, and the per-query
+// constants of the scan filter.
 template <int M>
 __device__ __forceinline__ void sample_select_body(const TopkArgs& a, int64_t q) {
   extern __shared__ uint32_t keys[];  // [S rounded up to 64]
